@@ -1,0 +1,141 @@
+/*
+ * gf2x_oracle.c -- plain, slow, obviously correct CPU reference for products
+ * in F2[X] and in the ring F2[X]/(X^n - 1).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file: only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or helper
+ * with the GPU library.
+ *
+ * What it computes (Robert & Veron, "Faster Multiplication over F2[X] using
+ * AVX512 instruction set and VPCLMULQDQ instruction"):
+ *   - Section 2.1 (KaratRec subsection): operands are binary polynomials of
+ *     degree at most N-1, packed into ceil(N/64) 64-bit words; their product
+ *     has degree at most 2N-2.  The product is the schoolbook definition
+ *     c_k = XOR_{i+j=k} a_i AND b_j, written out word by word.
+ *   - Section 1 (the circulant / ring discussion): the protocols need the
+ *     product in F2[X]/(X^N - 1).  Since X^N = 1 in that ring, bit k+N of the
+ *     full product lands on bit k: r_k = c_k XOR c_{k+N}.  One fold suffices
+ *     because deg c <= 2N-2.
+ *
+ * Packing (the paper fixes the word count, not the bit order; this library
+ * uses little-endian order): bit i of a polynomial is bit (i mod 64) of
+ * word floor(i/64).  Input bits >= n are ignored (masked on entry); output
+ * bits beyond the result's degree bound are written as zero.
+ *
+ * The 64x64 -> 128 carry-less multiply is the plain shift-and-XOR definition
+ * (the function PCLMULQDQ computes, Section 2.2.2): for every set bit k of x,
+ * XOR y shifted left by k into the 128-bit accumulator.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define WORDS(n) (((uint64_t)(n) + 63u) / 64u)
+
+/* Mask that keeps the n mod 64 valid bits of the top word (all ones when
+ * n is a multiple of 64). */
+static uint64_t top_mask(uint32_t n)
+{
+    uint32_t s = n % 64u;
+    return s == 0 ? ~(uint64_t)0 : (((uint64_t)1 << s) - 1u);
+}
+
+/* 64x64 -> 128 carry-less product, bit by bit.  The k = 0 step is kept
+ * apart because a C shift by 64 is undefined. */
+void gf2x_ref_clmul64(uint64_t x, uint64_t y, uint64_t *lo, uint64_t *hi)
+{
+    uint64_t l = 0, h = 0;
+    for (unsigned k = 0; k < 64; ++k) {
+        uint64_t m = (uint64_t)0 - ((x >> k) & 1u); /* all ones iff bit k of x */
+        l ^= (y << k) & m;
+        if (k > 0)
+            h ^= (y >> (64u - k)) & m;
+    }
+    *lo = l;
+    *hi = h;
+}
+
+/* Full product c = a*b in F2[X].  a, b: W(n) words each; c: 2*W(n) words.
+ * Word-level schoolbook: c[i+j] ^= lo(a_i*b_j), c[i+j+1] ^= hi(a_i*b_j).
+ * Returns 0, or -1 on a null pointer / n == 0. */
+int gf2x_ref_mul(uint64_t *c, const uint64_t *a, const uint64_t *b, uint32_t n)
+{
+    if (!c || !a || !b || n == 0)
+        return -1;
+    uint64_t W = WORDS(n);
+    uint64_t *x = (uint64_t *)malloc(W * sizeof(uint64_t));
+    uint64_t *y = (uint64_t *)malloc(W * sizeof(uint64_t));
+    if (!x || !y) {
+        free(x);
+        free(y);
+        return -2;
+    }
+    memcpy(x, a, W * sizeof(uint64_t));
+    memcpy(y, b, W * sizeof(uint64_t));
+    x[W - 1] &= top_mask(n);
+    y[W - 1] &= top_mask(n);
+    memset(c, 0, 2 * W * sizeof(uint64_t));
+    for (uint64_t i = 0; i < W; ++i)
+        for (uint64_t j = 0; j < W; ++j) {
+            uint64_t lo, hi;
+            gf2x_ref_clmul64(x[i], y[j], &lo, &hi);
+            c[i + j] ^= lo;
+            c[i + j + 1] ^= hi;
+        }
+    free(x);
+    free(y);
+    return 0;
+}
+
+/* Fold a full product (2*W(n) words, degree <= 2n-2) into the ring:
+ * r_k = c_k XOR c_{k+n} for 0 <= k < n.  Word k of (c >> n) is a funnel
+ * shift of words q+k and q+k+1 of c, q = floor(n/64), s = n mod 64; words
+ * at index >= 2W read as zero.  r: W(n) words. */
+int gf2x_ref_fold(uint64_t *r, const uint64_t *c, uint32_t n)
+{
+    if (!r || !c || n == 0)
+        return -1;
+    uint64_t W = WORDS(n);
+    uint64_t q = n / 64u, s = n % 64u;
+    for (uint64_t k = 0; k < W; ++k) {
+        uint64_t w0 = (k + q < 2 * W) ? c[k + q] : 0;
+        uint64_t w1 = (k + q + 1 < 2 * W) ? c[k + q + 1] : 0;
+        uint64_t h = (s == 0) ? w0 : ((w0 >> s) | (w1 << (64u - s)));
+        r[k] = c[k] ^ h;
+    }
+    r[W - 1] &= top_mask(n);
+    return 0;
+}
+
+/* Ring product r = a*b mod (X^n - 1): full product, then fold. */
+int gf2x_ref_mul_cyclic(uint64_t *r, const uint64_t *a, const uint64_t *b, uint32_t n)
+{
+    if (!r || !a || !b || n == 0)
+        return -1;
+    uint64_t W = WORDS(n);
+    uint64_t *c = (uint64_t *)malloc(2 * W * sizeof(uint64_t));
+    if (!c)
+        return -2;
+    int rc = gf2x_ref_mul(c, a, b, n);
+    if (rc == 0)
+        rc = gf2x_ref_fold(r, c, n);
+    free(c);
+    return rc;
+}
+
+/* Many independent ring products of one size, one after another:
+ * item i uses a + i*W, b + i*W and writes r + i*W.  Used to time the
+ * oracle on a sample of a batch. */
+int gf2x_ref_mul_cyclic_many(uint64_t *r, const uint64_t *a, const uint64_t *b,
+                             uint32_t n, uint32_t count)
+{
+    uint64_t W = WORDS(n);
+    for (uint32_t i = 0; i < count; ++i) {
+        int rc = gf2x_ref_mul_cyclic(r + (uint64_t)i * W, a + (uint64_t)i * W,
+                                     b + (uint64_t)i * W, n);
+        if (rc)
+            return rc;
+    }
+    return 0;
+}

@@ -1,0 +1,120 @@
+"""ctypes wrapper around the C oracle (``gf2x_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Operands are numpy
+``uint64`` arrays of ``words(n)`` little-endian words; bit i of a polynomial
+is bit i % 64 of word i // 64.
+"""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gf2x_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def words(n):
+    """Number of 64-bit words holding a polynomial of n coefficients."""
+    return (int(n) + 63) // 64
+
+
+def build():
+    """Compile the oracle with gcc -O2 into ``liboracle.so`` (always rebuilds)."""
+    tmp = _LIB + ".tmp"
+    subprocess.check_call(
+        ["gcc", "-O2", "-std=c99", "-Wall", "-Wextra", "-fPIC", "-shared", _SRC, "-o", tmp]
+    )
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def load():
+    """Load the built oracle, building it first only if it is absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        for name in ("gf2x_ref_mul", "gf2x_ref_mul_cyclic"):
+            fn = getattr(lib, name)
+            fn.restype = ctypes.c_int
+            fn.argtypes = [_u64p, _u64p, _u64p, ctypes.c_uint32]
+        lib.gf2x_ref_fold.restype = ctypes.c_int
+        lib.gf2x_ref_fold.argtypes = [_u64p, _u64p, ctypes.c_uint32]
+        lib.gf2x_ref_mul_cyclic_many.restype = ctypes.c_int
+        lib.gf2x_ref_mul_cyclic_many.argtypes = [_u64p, _u64p, _u64p, ctypes.c_uint32, ctypes.c_uint32]
+        lib.gf2x_ref_clmul64.restype = None
+        lib.gf2x_ref_clmul64.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _u64p, _u64p]
+        _lib = lib
+    return _lib
+
+
+def _ptr(arr):
+    return arr.ctypes.data_as(_u64p)
+
+
+def _as_words(x, n):
+    x = np.ascontiguousarray(x, dtype=np.uint64)
+    if x.shape != (words(n),):
+        raise ValueError("operand must hold exactly words(n) = %d words" % words(n))
+    return x
+
+
+def clmul64(x, y):
+    """Carry-less 64x64 -> 128 product; returns (lo, hi) as Python ints."""
+    lo = ctypes.c_uint64()
+    hi = ctypes.c_uint64()
+    load().gf2x_ref_clmul64(int(x), int(y), ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value
+
+
+def mul(a, b, n):
+    """Full product in F2[X]: returns 2*words(n) words."""
+    a = _as_words(a, n)
+    b = _as_words(b, n)
+    c = np.zeros(2 * words(n), dtype=np.uint64)
+    rc = load().gf2x_ref_mul(_ptr(c), _ptr(a), _ptr(b), int(n))
+    if rc:
+        raise RuntimeError("gf2x_ref_mul failed (%d)" % rc)
+    return c
+
+
+def fold(c, n):
+    """Reduce a full product (2*words(n) words) modulo X^n - 1."""
+    c = np.ascontiguousarray(c, dtype=np.uint64)
+    if c.shape != (2 * words(n),):
+        raise ValueError("full product must hold 2*words(n) words")
+    r = np.zeros(words(n), dtype=np.uint64)
+    rc = load().gf2x_ref_fold(_ptr(r), _ptr(c), int(n))
+    if rc:
+        raise RuntimeError("gf2x_ref_fold failed (%d)" % rc)
+    return r
+
+
+def mul_cyclic(a, b, n):
+    """Ring product a*b mod (X^n - 1): returns words(n) words."""
+    a = _as_words(a, n)
+    b = _as_words(b, n)
+    r = np.zeros(words(n), dtype=np.uint64)
+    rc = load().gf2x_ref_mul_cyclic(_ptr(r), _ptr(a), _ptr(b), int(n))
+    if rc:
+        raise RuntimeError("gf2x_ref_mul_cyclic failed (%d)" % rc)
+    return r
+
+
+def mul_cyclic_many(a, b, n):
+    """Ring products of row pairs: a, b are (count, words(n)) arrays."""
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    b = np.ascontiguousarray(b, dtype=np.uint64)
+    if a.ndim != 2 or a.shape != b.shape or a.shape[1] != words(n):
+        raise ValueError("operands must be (count, words(n)) arrays of equal shape")
+    r = np.zeros_like(a)
+    rc = load().gf2x_ref_mul_cyclic_many(_ptr(r), _ptr(a), _ptr(b), int(n), a.shape[0])
+    if rc:
+        raise RuntimeError("gf2x_ref_mul_cyclic_many failed (%d)" % rc)
+    return r
