@@ -1,0 +1,273 @@
+"""Throughput of ring products in F2[X]/(X^n - 1) on one MI355X.
+
+Workload (one step): 4096 independent dense x dense ring products at
+n = 17669 (277 uint64 words per operand), uniform seeded operands, all in
+one persistent launch (replayed from a cached HIP graph).  Reported value:
+products per second over the timed steps, inputs already resident in HBM.
+
+Also measured (reported under "extra"): the same batch at n = 57637, and
+both sizes as 4096 back-to-back single-product launches (one per product)
+for the batched / one-per-launch factor.
+
+roofline: the dominant kernel is the batched product kernel; it is bound by
+VALU integer throughput.  achieved = modelled algorithmic lane-ops of the
+schedule (base-case bit operations plus XOR passes, as reported by
+gf2x_schedule_info) x products per launch / mean launch time, measured with
+HIP events on the launch stream over the timed steps; peak = 256 CU x 64
+lanes x 2.4 GHz.
+
+cpu_baseline: the CPU oracle (word schoolbook + fold) timed on the host
+cores over a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "products/sec at n=17669 & 57637 (batched vs one-per-launch); % int-op roofline"
+VALU_PEAK = 256 * 64 * 2.4e9  # int32 lane-ops per second
+BATCH = 4096
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_batch(n, count, seed):
+    import numpy as np
+    import torch
+
+    from paper_2201_10473_amd import gf2x, inputs
+
+    W = gf2x.words(n)
+    A = inputs.dense_batch(n, count, seed, 0)
+    B = inputs.dense_batch(n, count, seed, 1)
+    items = gf2x.make_items(n, gf2x.KIND_CYCLIC, np.arange(count) * W, np.arange(count) * W, np.arange(count) * W)
+    dA = torch.from_numpy(A.ravel().view(np.int64)).cuda()
+    dB = torch.from_numpy(B.ravel().view(np.int64)).cuda()
+    dC = torch.zeros(count * W, dtype=torch.int64, device="cuda")
+    return A, B, items, dA, dB, dC
+
+
+def time_batched(ctx, n, count, steps, warmup, seed):
+    import torch
+
+    from paper_2201_10473_amd import gf2x
+
+    A, B, items, dA, dB, dC = make_batch(n, count, seed)
+    flags = gf2x.USE_GRAPH
+    stream = torch.cuda.current_stream()
+    for _ in range(max(warmup, 1)):
+        ctx.mul_batched(items, dC, dA, dB, flags, stream)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record(stream)
+        ctx.mul_batched(items, dC, dA, dB, flags, stream)
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launch_ms = sum(s.elapsed_time(e) for s, e in ev) / steps
+    return {"A": A, "B": B, "C": dC, "wall_s": wall, "launch_ms": launch_ms, "items": items}
+
+
+def time_one_per_launch(ctx, n, count, seed):
+    import torch
+
+    from paper_2201_10473_amd import gf2x
+
+    A, B, items, dA, dB, dC = make_batch(n, count, seed)
+    W = gf2x.words(n)
+    stream = torch.cuda.current_stream()
+    base_c, base_a, base_b = dC.data_ptr(), dA.data_ptr(), dB.data_ptr()
+    s = stream.cuda_stream
+    for i in range(8):  # warm-up
+        ctx.mul_cyclic(base_c + 8 * W * i, base_a + 8 * W * i, base_b + 8 * W * i, n, s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(count):
+        off = 8 * W * i
+        ctx.mul_cyclic(base_c + off, base_a + off, base_b + off, n, s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"A": A, "B": B, "C": dC, "wall_s": wall}
+
+
+def check_sample(res, n, count, k=6):
+    """Spot-check k items against the oracle and all items against parity."""
+    import numpy as np
+
+    import oracle
+
+    W = (n + 63) // 64
+    C = res["C"].cpu().numpy().view(np.uint64).reshape(count, W)
+    A, B = res["A"], res["B"]
+    par = lambda X: (np.bitwise_count(X).sum(axis=1) & 1)
+    if not np.array_equal(par(C), par(A) & par(B)):
+        raise AssertionError("parity invariant failed at n=%d" % n)
+    for i in np.linspace(0, count - 1, k).astype(int):
+        if not np.array_equal(C[i], oracle.mul_cyclic(A[i], B[i], n)):
+            raise AssertionError("item %d differs from the oracle at n=%d" % (i, n))
+
+
+def cpu_baseline(n, seed, target_s=12.0):
+    """Oracle throughput on the host cores over a bounded sample of the workload."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    import oracle
+    from paper_2201_10473_amd import inputs
+
+    oracle.load()
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    A = inputs.dense_batch(n, 1, seed, 0)
+    B = inputs.dense_batch(n, 1, seed, 1)
+    t0 = time.perf_counter()
+    oracle.mul_cyclic_many(A, B, n)
+    one = time.perf_counter() - t0
+    per_thread = max(1, int(target_s / threads / max(one, 1e-4)))
+    per_thread = min(per_thread, BATCH // threads if BATCH >= threads else 1)
+    total = per_thread * threads
+    A = inputs.dense_batch(n, total, seed, 0)
+    B = inputs.dense_batch(n, total, seed, 1)
+
+    def work(t):
+        sl = slice(t * per_thread, (t + 1) * per_thread)
+        return oracle.mul_cyclic_many(A[sl], B[sl], n)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(work, range(threads)))
+    wall = time.perf_counter() - t0
+    return {
+        "value": round(total / wall, 2),
+        "unit": "products/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": "%d ring products at n=%d (the first %d pairs of the seeded batch), %d threads x %d products"
+        % (total, n, total, threads, per_thread),
+    }
+
+
+def traffic_from_profile(kernel_key):
+    """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE),
+    if a summary for the current kernel sources is committed under profiles/."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except Exception:
+        return None
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2201_10473_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    entry = data.get(kernel_key)
+    if not entry or entry.get("sources_sha256") != h.hexdigest():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-one-per-launch", action="store_true")
+    ap.add_argument("--only-n", type=int, default=0, help="time only this ring size (profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU; multi-GPU runs are not part of this library's benchmark "
+              "(independent products shard by item with no exchange).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2201_10473_amd import gf2x, inputs
+
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    ctx = gf2x.Context(0)
+    seed = inputs.SEED_BASE + 2
+    sizes = [args.only_n] if args.only_n else [17669, 57637]
+    results = {}
+    for n in sizes:
+        s, base, ops, name = ctx.schedule_info(n)
+        log("batched n=%d schedule=%s ops/product=%d" % (n, name, ops))
+        r = time_batched(ctx, n, BATCH, args.steps, args.warmup, seed)
+        check_sample(r, n, BATCH)
+        res = {
+            "schedule": name,
+            "padded_words32": s,
+            "lane_ops_per_product": ops,
+            "launch_ms": r["launch_ms"],
+            "products_per_s": BATCH * args.steps / r["wall_s"],
+            "ms_per_step": 1e3 * r["wall_s"] / args.steps,
+        }
+        res["valu_frac"] = ops * BATCH / (res["launch_ms"] * 1e-3) / VALU_PEAK
+        if not args.no_one_per_launch and not args.only_n:
+            log("one-per-launch n=%d" % n)
+            o = time_one_per_launch(ctx, n, BATCH, seed)
+            check_sample(o, n, BATCH)
+            res["one_per_launch_products_per_s"] = BATCH / o["wall_s"]
+            res["batched_over_one_per_launch"] = res["products_per_s"] / res["one_per_launch_products_per_s"]
+        results[n] = res
+        log("n=%d: %.0f products/s, launch %.3f ms, VALU frac %.3f" % (n, res["products_per_s"], res["launch_ms"], res["valu_frac"]))
+
+    head = sizes[0]
+    main_res = results[head]
+    achieved = main_res["lane_ops_per_product"] * BATCH / (main_res["launch_ms"] * 1e-3)
+    roof = {
+        "bound": "alu",
+        "achieved": round(achieved / 1e12, 4),
+        "peak": round(VALU_PEAK / 1e12, 4),
+        "unit": "Tlane-op/s",
+        "frac": round(achieved / VALU_PEAK, 4),
+        "traffic": traffic_from_profile("batched_n%d" % head),
+        "kernel": "gf2x::k_batched<%s>" % main_res["schedule"],
+    }
+    out = {
+        "metric": METRIC,
+        "value": round(main_res["products_per_s"], 1),
+        "unit": "products/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "%d independent dense x dense ring products in F2[X]/(X^%d - 1), uniform seeded "
+            "operands of %d uint64 words, one persistent launch per step (HIP graph replay)"
+            % (BATCH, head, (head + 63) // 64),
+            "n": head,
+            "batch": BATCH,
+            "schedule": main_res["schedule"],
+        },
+        "roofline": roof,
+        "extra": {str(n): {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+                  for n, r in results.items()},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) n=%d" % head)
+        out["cpu_baseline"] = cpu_baseline(head, seed)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

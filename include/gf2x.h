@@ -1,0 +1,154 @@
+/*
+ * gf2x.h -- C ABI of the MI355X (gfx950) library for products of dense
+ * binary polynomials in F2[X] and in the ring F2[X]/(X^n - 1).
+ *
+ * Operation (Robert & Veron, "Faster Multiplication over F2[X] using AVX512
+ * instruction set and VPCLMULQDQ instruction"):
+ *   - Section 2.1: two binary polynomials of degree at most n-1, each packed
+ *     into ceil(n/64) 64-bit words, are multiplied; the product has degree at
+ *     most 2n-2.
+ *   - Section 1 (circulant matrices and the ring F2[X]/(X^N - 1)): the
+ *     code-based KEMs need that product reduced modulo X^n - 1, i.e. bit k+n
+ *     of the full product is added to bit k.
+ *   - Appendix A (Karatsuba 2-, 3- and 5-way splits) and Section 3 with
+ *     Appendix D (word-aligned Toom-Cook 3 with evaluation points 0, 1, x,
+ *     x+1, infinity and exact divisions by x and x+1) are the recursions the
+ *     GPU kernels use; the result does not depend on which one is chosen.
+ *
+ * Layout.  A polynomial of n coefficients occupies W(n) = ceil(n/64)
+ * uint64 words, little-endian: coefficient i is bit (i mod 64) of word
+ * floor(i/64).  Input bits at positions >= n are ignored (masked on load).
+ * Output bits beyond the result's degree bound are written as zero: bits >= n
+ * for ring products, bits >= 2n-1 for full products.
+ *
+ * Pointers.  Every operand and result pointer is a DEVICE pointer (memory
+ * from hipMalloc or equivalent on the context's device), 8-byte aligned.
+ * Items and options passed by pointer are HOST memory unless a flag says
+ * otherwise.  The caller owns every buffer and keeps it alive until the
+ * stream has passed the call.
+ *
+ * Streams and synchronisation.  Calls enqueue work on the given HIP stream
+ * (NULL = the default stream) and return; they never wait for the device and
+ * never read device memory from the host.  One context may be used from one
+ * host thread at a time.
+ *
+ * Constant time.  Control flow, loop bounds and every memory address inside
+ * the kernels depend only on n (public); never on operand bits.
+ *
+ * Errors.  Every entry point returns 0 on success or a negative GF2X_E* code;
+ * no exception crosses the ABI.  On error nothing has been enqueued.
+ */
+#ifndef GF2X_H
+#define GF2X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+struct ihipStream_t;                       /* hipStream_t is a pointer to this */
+typedef struct ihipStream_t *gf2x_stream_t;
+
+#define GF2X_OK 0
+#define GF2X_EINVAL (-1)  /* bad argument: null pointer, n out of range, misaligned or overlapping buffers */
+#define GF2X_ENOMEM (-2)  /* a device workspace could not be allocated                                     */
+#define GF2X_EDEVICE (-3) /* a HIP runtime call failed; gf2x_last_device_error() names it                   */
+#define GF2X_ENOTSUP (-5) /* the request is valid but this build cannot serve it (see gf2x_mul_batched)    */
+
+/* Largest supported n, in bits (the paper's largest operand size, Table perfKaratRec). */
+#define GF2X_MAX_BITS 131072u
+
+/* Item kinds for gf2x_mul_batched. */
+#define GF2X_KIND_CYCLIC 0u /* c: W(n) words, c = a*b mod (X^n - 1) */
+#define GF2X_KIND_FULL 1u   /* c: 2*W(n) words, c = a*b in F2[X]    */
+
+/* Flags for gf2x_mul_batched. */
+#define GF2X_ITEMS_ON_DEVICE 0x1u  /* `items` is a device pointer (not validated on the host)               */
+#define GF2X_SHARED_A 0x2u         /* every item has the same a_off and n (one operand shared by the batch) */
+#define GF2X_FORCE_PACKED 0x4u     /* use the bit-packed Karatsuba/Toom path even when GF2X_SHARED_A is set */
+#define GF2X_FORCE_TOEPLITZ 0x8u   /* with GF2X_SHARED_A: use the Toeplitz int8-MFMA path                   */
+#define GF2X_USE_GRAPH 0x10u       /* replay a cached HIP graph of the launch (host items only)             */
+
+typedef struct gf2x_ctx gf2x_ctx;
+
+typedef struct gf2x_opts {
+    int device;              /* HIP device ordinal the context's work runs on                         */
+    size_t hbm_budget_bytes; /* cap on the context's own device workspace (0 = 1 GiB)                 */
+    const char *tune_cache;  /* path of the schedule table written by the tuner, or NULL for defaults */
+    uint32_t flags;          /* reserved, must be 0                                                   */
+} gf2x_opts;
+
+/* One product of a batch.  Offsets count uint64 words from the base pointers
+ * given to gf2x_mul_batched; operands hold W(n_bits) words. */
+typedef struct gf2x_item {
+    uint32_t n_bits; /* 1 <= n_bits <= GF2X_MAX_BITS */
+    uint32_t kind;   /* GF2X_KIND_CYCLIC or GF2X_KIND_FULL */
+    uint64_t a_off, b_off, c_off;
+} gf2x_item;
+
+/* Create a context on opts->device (opts may be NULL: device 0, defaults).
+ * *out receives the context.  Errors: GF2X_EINVAL, GF2X_EDEVICE. */
+int gf2x_create(gf2x_ctx **out, const gf2x_opts *opts);
+
+/* Release a context and its device workspace.  The caller must make sure no
+ * enqueued work still uses it.  NULL is accepted. */
+void gf2x_destroy(gf2x_ctx *ctx);
+
+/* Full product c = a*b in F2[X] (Section 2.1).
+ * a, b: W(n) words each; c: 2*W(n) words (bits >= 2n-1 written zero).
+ * c must not overlap a or b.  Errors: GF2X_EINVAL, GF2X_EDEVICE. */
+int gf2x_mul(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b,
+             uint32_t n_bits, gf2x_stream_t stream);
+
+/* Ring product c = a*b mod (X^n - 1) (Section 1).  a, b, c: W(n) words each;
+ * bits >= n of c written zero.  c must not overlap a or b.
+ * Errors: GF2X_EINVAL, GF2X_EDEVICE. */
+int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b,
+                    uint32_t n_bits, gf2x_stream_t stream);
+
+/* `count` independent products in one persistent launch.  Item i reads
+ * a_base + items[i].a_off and b_base + items[i].b_off and writes
+ * c_base + items[i].c_off (sizes per its kind).  Items may mix sizes and
+ * kinds.  With host items (default) the library validates n and kind, sorts
+ * the work by decreasing n and copies the descriptors to its workspace;
+ * with GF2X_ITEMS_ON_DEVICE the descriptors are used as given and must be
+ * valid.  Output ranges of different items must not overlap each other or
+ * any operand range.
+ * GF2X_SHARED_A (all items share a_off, n and kind == CYCLIC) lets the
+ * library pick the Toeplitz MFMA path for that batch; the FORCE flags pin
+ * the choice.  GF2X_USE_GRAPH captures the launch sequence in a HIP graph the
+ * first time a given (items, count, bases, flags, stream) is seen and
+ * replays it afterwards; the host item array must then stay unchanged.
+ * count == 0 is a no-op.
+ * Errors: GF2X_EINVAL, GF2X_ENOMEM, GF2X_EDEVICE, GF2X_ENOTSUP (FORCE_TOEPLITZ
+ * without SHARED_A, or device items with GF2X_USE_GRAPH). */
+int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count,
+                     uint64_t *c_base, const uint64_t *a_base, const uint64_t *b_base,
+                     uint32_t flags, gf2x_stream_t stream);
+
+/* Schedule the library uses for n: the padded operand size in 32-bit words,
+ * the number of 32x32-bit word products computed by the base case, the
+ * algorithmic VALU lane-op count of one product (per-schedule cost model:
+ * base-case bit operations plus one op per word of every XOR pass), and the
+ * schedule's name.  ctx may be NULL (then the built-in default table is used;
+ * no device is touched).  Any output pointer may be NULL.  Host only.
+ * Errors: GF2X_EINVAL. */
+int gf2x_schedule_info(gf2x_ctx *ctx, uint32_t n_bits, uint32_t *padded_words32,
+                       uint64_t *base_products, uint64_t *lane_ops, char *name, size_t name_len);
+
+/* Static message for a GF2X_E* code. */
+const char *gf2x_strerror(int code);
+
+/* Name of the last HIP error seen by this thread's calls ("" if none). */
+const char *gf2x_last_device_error(void);
+
+/* Library version, as 10000*major + 100*minor + patch. */
+int gf2x_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF2X_H */

@@ -1,0 +1,386 @@
+// gf2x_api.cpp -- the C ABI declared in include/gf2x.h: argument checks,
+// per-size schedule table, workspace and graph cache, launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "gf2x.h"
+#include "gf2x_internal.hpp"
+#include "gf2x_toeplitz.hpp"
+
+using namespace gf2x;
+
+namespace {
+
+thread_local std::string g_last_device_error;
+
+int device_error(hipError_t e) {
+    g_last_device_error = hipGetErrorName(e);
+    g_last_device_error += ": ";
+    g_last_device_error += hipGetErrorString(e);
+    return GF2X_EDEVICE;
+}
+
+#define HIP_TRY(expr)                              \
+    do {                                           \
+        hipError_t _e = (expr);                    \
+        if (_e != hipSuccess) return device_error(_e); \
+    } while (0)
+
+uint64_t words64(uint32_t n) { return ((uint64_t)n + 63u) / 64u; }
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    DevItem *items = nullptr;  // private copy of the descriptors
+    uint64_t checksum = 0;
+};
+
+}  // namespace
+
+struct gf2x_ctx {
+    int device = 0;
+    int num_cu = 0;
+    size_t budget = 0;
+    size_t allocated = 0;
+    int cls_of_w32[kMaxWords32 + 1];
+    uint8_t *d_cls = nullptr;      // device copy of cls_of_w32
+    DevItem *d_items = nullptr;    // workspace for host item descriptors
+    size_t d_items_cap = 0;
+    hipEvent_t ws_free = nullptr;  // recorded after the last launch reading d_items
+    bool ws_used = false;
+    std::map<std::tuple<const void *, uint32_t, const void *, const void *, const void *, uint32_t, void *>,
+             GraphEntry>
+        graphs;
+    toeplitz::Workspace tz;
+};
+
+namespace {
+
+// Default schedule choice: among the classes whose padded size holds w
+// 32-bit words, the one with the fewest modelled lane-ops.
+int default_class(uint32_t w) {
+    int best = -1;
+    long long best_ops = 0;
+    for (int c = 0; c < kNumClasses; ++c) {
+        const ClassInfo &ci = class_info(c);
+        if ((uint32_t)ci.S < std::max<uint32_t>(w, 1)) continue;
+        if (best < 0 || ci.ops < best_ops) {
+            best = c;
+            best_ops = ci.ops;
+        }
+    }
+    return best;
+}
+
+void default_table(gf2x_ctx *ctx) {
+    for (uint32_t w = 0; w <= kMaxWords32; ++w) ctx->cls_of_w32[w] = default_class(w);
+}
+
+// Tuner cache: text lines "w32 class_name" override the default per size.
+int load_tune_cache(gf2x_ctx *ctx, const char *path) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return GF2X_OK;  // no cache yet: defaults
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        unsigned w = 0;
+        char name[128];
+        if (line[0] == '#' || std::sscanf(line, "%u %127s", &w, name) != 2) continue;
+        if (w == 0 || w > kMaxWords32) continue;
+        for (int c = 0; c < kNumClasses; ++c)
+            if (std::strcmp(class_info(c).name, name) == 0 && (uint32_t)class_info(c).S >= w)
+                ctx->cls_of_w32[w] = c;
+    }
+    std::fclose(f);
+    return GF2X_OK;
+}
+
+bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
+
+bool overlap(const void *x, uint64_t xw, const void *y, uint64_t yw) {
+    const uintptr_t a0 = (uintptr_t)x, a1 = a0 + xw * 8, b0 = (uintptr_t)y, b1 = b0 + yw * 8;
+    return a0 < b1 && b0 < a1;
+}
+
+int check_single(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b, uint32_t n, uint64_t cw) {
+    if (!ctx || !c || !a || !b) return GF2X_EINVAL;
+    if (n == 0 || n > kMaxBits) return GF2X_EINVAL;
+    if (!aligned8(c) || !aligned8(a) || !aligned8(b)) return GF2X_EINVAL;
+    const uint64_t W = words64(n);
+    if (overlap(c, cw, a, W) || overlap(c, cw, b, W)) return GF2X_EINVAL;
+    return GF2X_OK;
+}
+
+int ensure_items(gf2x_ctx *ctx, size_t count) {
+    if (count <= ctx->d_items_cap) return GF2X_OK;
+    size_t cap = std::max<size_t>(count, 2 * ctx->d_items_cap);
+    const size_t bytes = cap * sizeof(DevItem);
+    if (ctx->allocated - ctx->d_items_cap * sizeof(DevItem) + bytes > ctx->budget) return GF2X_ENOMEM;
+    if (ctx->d_items) {
+        // the old buffer may still be read by enqueued work
+        HIP_TRY(hipEventSynchronize(ctx->ws_free));
+        HIP_TRY(hipFree(ctx->d_items));
+        ctx->allocated -= ctx->d_items_cap * sizeof(DevItem);
+        ctx->d_items = nullptr;
+        ctx->d_items_cap = 0;
+    }
+    if (hipMalloc(&ctx->d_items, bytes) != hipSuccess) return GF2X_ENOMEM;
+    ctx->d_items_cap = cap;
+    ctx->allocated += bytes;
+    return GF2X_OK;
+}
+
+uint64_t checksum(const gf2x_item *items, uint32_t count) {
+    uint64_t h = 1469598103934665603ull;
+    const unsigned char *p = reinterpret_cast<const unsigned char *>(items);
+    for (size_t i = 0; i < (size_t)count * sizeof(gf2x_item); ++i) h = (h ^ p[i]) * 1099511628211ull;
+    return h;
+}
+
+// Host descriptors -> validated DevItems ordered by decreasing n (stable).
+int build_items(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, std::vector<DevItem> &out, bool &uniform,
+                int &cls0, int &max_lds) {
+    out.resize(count);
+    uniform = true;
+    cls0 = -1;
+    max_lds = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        const gf2x_item &it = items[i];
+        if (it.n_bits == 0 || it.n_bits > kMaxBits) return GF2X_EINVAL;
+        if (it.kind != GF2X_KIND_CYCLIC && it.kind != GF2X_KIND_FULL) return GF2X_EINVAL;
+        const int cls = ctx->cls_of_w32[(it.n_bits + 31u) / 32u];
+        out[i] = DevItem{it.n_bits, it.kind, (uint32_t)cls, 0u, it.a_off, it.b_off, it.c_off};
+        if (cls0 < 0) cls0 = cls;
+        if (cls != cls0) uniform = false;
+        max_lds = std::max(max_lds, class_info(cls).lds_bytes);
+    }
+    if (!uniform)
+        std::stable_sort(out.begin(), out.end(), [](const DevItem &x, const DevItem &y) { return x.n > y.n; });
+    return GF2X_OK;
+}
+
+int launch_items(gf2x_ctx *ctx, const DevItem *d_items, uint32_t count, bool uniform, int cls0, int max_lds,
+                 uint64_t *c, const uint64_t *a, const uint64_t *b, hipStream_t s) {
+    hipError_t e;
+    if (uniform) e = launch_batched(cls0, d_items, count, c, a, b, ctx->num_cu, s);
+    else e = launch_mixed(d_items, count, c, a, b, ctx->d_cls, false, max_lds, ctx->num_cu, s);
+    if (e != hipSuccess) return device_error(e);
+    return GF2X_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gf2x_version(void) { return 10000; }
+
+const char *gf2x_strerror(int code) {
+    switch (code) {
+        case GF2X_OK: return "success";
+        case GF2X_EINVAL: return "invalid argument";
+        case GF2X_ENOMEM: return "device workspace exceeds the budget or could not be allocated";
+        case GF2X_EDEVICE: return "HIP runtime error";
+        case GF2X_ENOTSUP: return "unsupported combination of flags";
+        default: return "unknown error code";
+    }
+}
+
+const char *gf2x_last_device_error(void) { return g_last_device_error.c_str(); }
+
+int gf2x_create(gf2x_ctx **out, const gf2x_opts *opts) {
+    if (!out) return GF2X_EINVAL;
+    *out = nullptr;
+    gf2x_opts o{};
+    if (opts) o = *opts;
+    if (o.flags != 0) return GF2X_EINVAL;
+    int ndev = 0;
+    HIP_TRY(hipGetDeviceCount(&ndev));
+    if (o.device < 0 || o.device >= ndev) return GF2X_EINVAL;
+    HIP_TRY(hipSetDevice(o.device));
+    gf2x_ctx *ctx = new (std::nothrow) gf2x_ctx();
+    if (!ctx) return GF2X_ENOMEM;
+    ctx->device = o.device;
+    ctx->budget = o.hbm_budget_bytes ? o.hbm_budget_bytes : ((size_t)1 << 30);
+    hipDeviceProp_t prop;
+    hipError_t e = hipGetDeviceProperties(&prop, o.device);
+    if (e == hipSuccess) e = prepare_kernels();
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ws_free, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        delete ctx;
+        return device_error(e);
+    }
+    ctx->num_cu = prop.multiProcessorCount;
+    default_table(ctx);
+    if (o.tune_cache) load_tune_cache(ctx, o.tune_cache);
+    uint8_t tab[kMaxWords32 + 1];
+    for (uint32_t w = 0; w <= kMaxWords32; ++w) tab[w] = (uint8_t)ctx->cls_of_w32[w];
+    e = hipMalloc(&ctx->d_cls, sizeof tab);
+    if (e == hipSuccess) e = hipMemcpy(ctx->d_cls, tab, sizeof tab, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        gf2x_destroy(ctx);
+        return device_error(e);
+    }
+    ctx->allocated += sizeof tab;
+    *out = ctx;
+    return GF2X_OK;
+}
+
+void gf2x_destroy(gf2x_ctx *ctx) {
+    if (!ctx) return;
+    hipSetDevice(ctx->device);
+    for (auto &kv : ctx->graphs) {
+        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
+        if (kv.second.graph) hipGraphDestroy(kv.second.graph);
+        if (kv.second.items) hipFree(kv.second.items);
+    }
+    toeplitz::release(ctx->tz);
+    if (ctx->d_items) hipFree(ctx->d_items);
+    if (ctx->d_cls) hipFree(ctx->d_cls);
+    if (ctx->ws_free) hipEventDestroy(ctx->ws_free);
+    delete ctx;
+}
+
+int gf2x_mul(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b, uint32_t n_bits,
+             gf2x_stream_t stream) {
+    int rc = check_single(ctx, c, a, b, n_bits, 2 * words64(n_bits));
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int cls = ctx->cls_of_w32[(n_bits + 31u) / 32u];
+    HIP_TRY(launch_single(cls, a, b, c, n_bits, kKindFull, reinterpret_cast<hipStream_t>(stream)));
+    return GF2X_OK;
+}
+
+int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b, uint32_t n_bits,
+                    gf2x_stream_t stream) {
+    int rc = check_single(ctx, c, a, b, n_bits, words64(n_bits));
+    if (rc) return rc;
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int cls = ctx->cls_of_w32[(n_bits + 31u) / 32u];
+    HIP_TRY(launch_single(cls, a, b, c, n_bits, kKindCyclic, reinterpret_cast<hipStream_t>(stream)));
+    return GF2X_OK;
+}
+
+int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint64_t *c_base,
+                     const uint64_t *a_base, const uint64_t *b_base, uint32_t flags, gf2x_stream_t stream) {
+    if (!ctx) return GF2X_EINVAL;
+    if (count == 0) return GF2X_OK;
+    if (!items || !c_base || !a_base || !b_base) return GF2X_EINVAL;
+    if (!aligned8(c_base) || !aligned8(a_base) || !aligned8(b_base)) return GF2X_EINVAL;
+    const uint32_t known = GF2X_ITEMS_ON_DEVICE | GF2X_SHARED_A | GF2X_FORCE_PACKED | GF2X_FORCE_TOEPLITZ |
+                           GF2X_USE_GRAPH;
+    if (flags & ~known) return GF2X_EINVAL;
+    if ((flags & GF2X_FORCE_PACKED) && (flags & GF2X_FORCE_TOEPLITZ)) return GF2X_EINVAL;
+    if ((flags & GF2X_FORCE_TOEPLITZ) && !(flags & GF2X_SHARED_A)) return GF2X_ENOTSUP;
+    const bool dev_items = (flags & GF2X_ITEMS_ON_DEVICE) != 0;
+    if (dev_items && (flags & (GF2X_USE_GRAPH | GF2X_SHARED_A))) return GF2X_ENOTSUP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipSetDevice(ctx->device));
+
+    if (dev_items) {
+        // Descriptors stay on the device; the class comes from the size table.
+        int rc = ensure_items(ctx, count);
+        if (rc) return rc;
+        if (ctx->ws_used) HIP_TRY(hipStreamWaitEvent(s, ctx->ws_free, 0));
+        HIP_TRY(launch_convert_items(items, count, ctx->d_items, s));
+        HIP_TRY(launch_mixed(ctx->d_items, count, c_base, a_base, b_base, ctx->d_cls, true, 160 * 1024,
+                             ctx->num_cu, s));
+        HIP_TRY(hipEventRecord(ctx->ws_free, s));
+        ctx->ws_used = true;
+        return GF2X_OK;
+    }
+
+    // Host descriptors: validate, order by decreasing n, pick the path.
+    if (flags & GF2X_SHARED_A) {
+        for (uint32_t i = 0; i < count; ++i)
+            if (items[i].a_off != items[0].a_off || items[i].n_bits != items[0].n_bits ||
+                items[i].kind != GF2X_KIND_CYCLIC)
+                return GF2X_EINVAL;
+        if (items[0].n_bits == 0 || items[0].n_bits > kMaxBits) return GF2X_EINVAL;
+        if (flags & GF2X_FORCE_TOEPLITZ) {
+            int rc = toeplitz::run(ctx->tz, ctx->budget, ctx->allocated, items, count, c_base, a_base, b_base,
+                                   ctx->num_cu, s);
+            if (rc == GF2X_EDEVICE) g_last_device_error = toeplitz::last_error();
+            return rc;
+        }
+    }
+    std::vector<DevItem> host;
+    bool uniform = true;
+    int cls0 = -1, max_lds = 0;
+    int rc = build_items(ctx, items, count, host, uniform, cls0, max_lds);
+    if (rc) return rc;
+
+    if (flags & GF2X_USE_GRAPH) {
+        auto key = std::make_tuple((const void *)items, count, (const void *)c_base, (const void *)a_base,
+                                   (const void *)b_base, flags, (void *)s);
+        const uint64_t sum = checksum(items, count);
+        auto it = ctx->graphs.find(key);
+        if (it != ctx->graphs.end() && it->second.checksum != sum) {
+            hipGraphExecDestroy(it->second.exec);
+            hipGraphDestroy(it->second.graph);
+            hipFree(it->second.items);
+            ctx->graphs.erase(it);
+            it = ctx->graphs.end();
+        }
+        if (it == ctx->graphs.end()) {
+            GraphEntry g;
+            g.checksum = sum;
+            if (hipMalloc(&g.items, count * sizeof(DevItem)) != hipSuccess) return GF2X_ENOMEM;
+            HIP_TRY(hipMemcpyAsync(g.items, host.data(), count * sizeof(DevItem), hipMemcpyHostToDevice, s));
+            // capture the launch on a private stream, ordered after the copy
+            hipStream_t cap;
+            HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                int lrc = launch_items(ctx, g.items, count, uniform, cls0, max_lds, c_base, a_base, b_base, cap);
+                hipError_t e2 = hipStreamEndCapture(cap, &g.graph);
+                if (lrc) e = hipErrorLaunchFailure;
+                else e = e2;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+            hipStreamDestroy(cap);
+            if (e != hipSuccess) {
+                if (g.graph) hipGraphDestroy(g.graph);
+                hipFree(g.items);
+                return device_error(e);
+            }
+            it = ctx->graphs.emplace(key, g).first;
+        }
+        HIP_TRY(hipGraphLaunch(it->second.exec, s));
+        return GF2X_OK;
+    }
+
+    rc = ensure_items(ctx, count);
+    if (rc) return rc;
+    if (ctx->ws_used) HIP_TRY(hipStreamWaitEvent(s, ctx->ws_free, 0));
+    HIP_TRY(hipMemcpyAsync(ctx->d_items, host.data(), count * sizeof(DevItem), hipMemcpyHostToDevice, s));
+    rc = launch_items(ctx, ctx->d_items, count, uniform, cls0, max_lds, c_base, a_base, b_base, s);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(ctx->ws_free, s));
+    ctx->ws_used = true;
+    return GF2X_OK;
+}
+
+int gf2x_schedule_info(gf2x_ctx *ctx, uint32_t n_bits, uint32_t *padded_words32, uint64_t *base_products,
+                       uint64_t *lane_ops, char *name, size_t name_len) {
+    if (n_bits == 0 || n_bits > kMaxBits) return GF2X_EINVAL;
+    const uint32_t w = (n_bits + 31u) / 32u;
+    const ClassInfo &ci = class_info(ctx ? ctx->cls_of_w32[w] : default_class(w));
+    if (padded_words32) *padded_words32 = (uint32_t)ci.S;
+    if (base_products) *base_products = (uint64_t)ci.base;
+    if (lane_ops) *lane_ops = (uint64_t)ci.ops;
+    if (name && name_len) {
+        std::strncpy(name, ci.name, name_len - 1);
+        name[name_len - 1] = 0;
+    }
+    return GF2X_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,47 @@
+// gf2x_internal.hpp -- interface between the C ABI layer (gf2x_api.cpp) and
+// the kernel translation unit (gf2x_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gf2x.h"
+
+namespace gf2x {
+
+constexpr int kNumClasses = 21;
+constexpr uint32_t kKindCyclic = 0;
+constexpr uint32_t kKindFull = 1;
+constexpr uint32_t kMaxBits = 131072;
+constexpr uint32_t kMaxWords32 = kMaxBits / 32;
+
+// Device-side descriptor of one batch item (offsets in uint64 words).
+struct DevItem {
+    uint32_t n;
+    uint32_t kind;
+    uint32_t cls;
+    uint32_t pad;
+    uint64_t a_off, b_off, c_off;
+};
+
+struct ClassInfo {
+    int id;
+    const char *name;
+    int S;                   // padded operand size, 32-bit words
+    int lds_bytes;           // LDS of one workgroup
+    long long base;          // 32x32 word products per multiplication
+    long long ops;           // algorithmic VALU lane-ops per multiplication
+};
+
+const ClassInfo &class_info(int cls);
+hipError_t prepare_kernels();
+hipError_t launch_single(int cls, const uint64_t *a, const uint64_t *b, uint64_t *c, uint32_t n, uint32_t kind,
+                         hipStream_t s);
+hipError_t launch_batched(int cls, const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
+                          const uint64_t *b_base, int num_cu, hipStream_t s);
+hipError_t launch_convert_items(const struct gf2x_item *items, uint32_t count, DevItem *out, hipStream_t s);
+hipError_t launch_mixed(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
+                        const uint64_t *b_base, const uint8_t *cls_of_w32, bool use_table, int lds_bytes,
+                        int num_cu, hipStream_t s);
+
+}  // namespace gf2x

@@ -1,0 +1,153 @@
+// gf2x_product.hpp -- one product per workgroup: staging, the size-class
+// table of schedules, and the ring / full epilogues.
+//
+// One workgroup computes one product: it stages both operands (masked to n
+// bits) from HBM into LDS as 32-bit words, runs the compile-time schedule of
+// its size class (gf2x_device.hpp), then either folds the 2n-1 bit product
+// modulo X^n - 1 in LDS and stores n bits (ring product, Section 1) or stores
+// the full product (Section 2.1).  The full product of a ring multiplication
+// never reaches HBM.
+//
+// Size classes: every class is a schedule with a fixed padded operand size
+// S (32-bit words); a product of n bits runs in any class with S >= ceil(n/32)
+// (zero padding does not change the product).  The host picks the class per
+// n from a table (default cost model, or the tuner's measurements).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gf2x_device.hpp"
+#include "gf2x_internal.hpp"
+
+namespace gf2x {
+
+// ------------------------------------------------------------ size classes
+using Class0 = ParK2<0, 4>;
+using Class1 = ParK2<0, 8>;
+using Class2 = ParK2<1, 8>;
+using Class3 = ParK2<2, 8>;
+using Class4 = ParK2<3, 8>;
+using Class5 = ParK2<4, 8>;
+using Class6 = ParK2<5, 8>;
+using Class7 = ParK2<5, 13>;
+using Class8 = SeqT3<ParK2<4, 9>>;
+using Class9 = SeqT3<ParK2<5, 5>>;
+using Class10 = SeqT3<ParK2<5, 6>>;
+using Class11 = SeqT3<ParK2<4, 12>>;
+using Class12 = SeqT3<SeqT3<ParK2<5, 3>>>;
+using Class13 = SeqT3<ParK2<5, 9>>;
+using Class14 = SeqT3<SeqT3<ParK2<5, 4>>>;
+using Class15 = SeqT3<SeqT3<ParK2<5, 5>>>;
+using Class16 = SeqT3<SeqT3<ParK2<4, 13>>>;
+using Class17 = SeqT3<SeqT3<ParK2<5, 7>>>;
+using Class18 = SeqT3<SeqT3<ParK2<5, 10>>>;
+using Class19 = SeqT3<SeqT3<SeqT3<ParK2<5, 4>>>>;
+using Class20 = SeqT3<SeqT3<SeqT3<ParK2<5, 5>>>>;
+
+// X(id, name, schedule type)
+#define GF2X_CLASS_LIST(X) \
+    X(0, "U4", Class0) \
+    X(1, "U8", Class1) \
+    X(2, "K2^1.U8", Class2) \
+    X(3, "K2^2.U8", Class3) \
+    X(4, "K2^3.U8", Class4) \
+    X(5, "K2^4.U8", Class5) \
+    X(6, "K2^5.U8", Class6) \
+    X(7, "K2^5.U13", Class7) \
+    X(8, "T3.K2^4.U9", Class8) \
+    X(9, "T3.K2^5.U5", Class9) \
+    X(10, "T3.K2^5.U6", Class10) \
+    X(11, "T3.K2^4.U12", Class11) \
+    X(12, "T3.T3.K2^5.U3", Class12) \
+    X(13, "T3.K2^5.U9", Class13) \
+    X(14, "T3.T3.K2^5.U4", Class14) \
+    X(15, "T3.T3.K2^5.U5", Class15) \
+    X(16, "T3.T3.K2^4.U13", Class16) \
+    X(17, "T3.T3.K2^5.U7", Class17) \
+    X(18, "T3.T3.K2^5.U10", Class18) \
+    X(19, "T3.T3.T3.K2^5.U4", Class19) \
+    X(20, "T3.T3.T3.K2^5.U5", Class20)
+
+#define GF2X_COUNT_CLASS(id, name, T) +1
+constexpr int NUM_CLASSES = 0 GF2X_CLASS_LIST(GF2X_COUNT_CLASS);
+static_assert(NUM_CLASSES == kNumClasses, "class count mismatch");
+
+template <class Sch>
+constexpr int lds_words() { return 2 * Sch::S + Sch::SCRATCH; }
+
+#define GF2X_CHECK_LDS(id, name, T) \
+    static_assert(lds_words<T>() * 4 <= 160 * 1024, "class " name " exceeds LDS");
+GF2X_CLASS_LIST(GF2X_CHECK_LDS)
+
+// --------------------------------------------------------- one product
+__device__ __forceinline__ u32 load_word32(const uint64_t *src, int k) {
+    return reinterpret_cast<const u32 *>(src)[k];
+}
+
+// Stage a and b (n bits each) into [A | B] as S zero-padded 32-bit words.
+template <int S>
+__device__ __forceinline__ void stage(const uint64_t *a, const uint64_t *b, u32 n, u32 *smem) {
+    const int w32 = (int)((n + 31u) / 32u);
+    const u32 s = n % 32u;
+    const u32 top = s ? ((1u << s) - 1u) : 0xFFFFFFFFu;
+    for (int k = threadIdx.x; k < S; k += NT) {
+        u32 x = 0, y = 0;
+        if (k < w32) {
+            x = load_word32(a, k);
+            y = load_word32(b, k);
+            if (k == w32 - 1) {
+                x &= top;
+                y &= top;
+            }
+        }
+        smem[k] = x;
+        smem[S + k] = y;
+    }
+}
+
+// Ring product epilogue: out32[k] = R[k] ^ (R >> n)[k] for k < ceil(n/32),
+// zero for the remaining 32-bit halves of the W(n) output words.
+template <int S>
+__device__ __forceinline__ void store_cyclic(const u32 *R, u32 n, uint64_t *c) {
+    const int w32 = (int)((n + 31u) / 32u);
+    const int out32 = 2 * (int)((n + 63u) / 64u);
+    const int q = (int)(n / 32u);
+    const u32 s = n % 32u;
+    const u32 top = s ? ((1u << s) - 1u) : 0xFFFFFFFFu;
+    u32 *c32 = reinterpret_cast<u32 *>(c);
+    for (int k = threadIdx.x; k < out32; k += NT) {
+        u32 v = 0;
+        if (k < w32) {
+            const int i0 = k + q, i1 = k + q + 1;
+            const u32 lo = i0 < 2 * S ? R[i0] : 0u;
+            const u32 hi = i1 < 2 * S ? R[i1] : 0u;
+            v = R[k] ^ funnel(hi, lo, s);
+            if (k == w32 - 1) v &= top;
+        }
+        c32[k] = v;
+    }
+}
+
+// Full product epilogue: 2*W(n) output words; R holds 2S words and every
+// bit at or above 2n-1 is zero.
+template <int S>
+__device__ __forceinline__ void store_full(const u32 *R, u32 n, uint64_t *c) {
+    const int out32 = 4 * (int)((n + 63u) / 64u);
+    u32 *c32 = reinterpret_cast<u32 *>(c);
+    for (int k = threadIdx.x; k < out32; k += NT) c32[k] = k < 2 * S ? R[k] : 0u;
+}
+
+template <class Sch>
+__device__ __forceinline__ void one_product(const uint64_t *a, const uint64_t *b, uint64_t *c, u32 n,
+                                            u32 kind, u32 *smem) {
+    constexpr int S = Sch::S;
+    stage<S>(a, b, n, smem);
+    __syncthreads();
+    const u32 *R = Sch::run(smem, smem + 2 * S);
+    if (kind == kKindCyclic) store_cyclic<S>(R, n, c);
+    else store_full<S>(R, n, c);
+    __syncthreads();  // LDS is reused by the next product of a persistent loop
+}
+
+}  // namespace gf2x

@@ -1,0 +1,28 @@
+// gf2x_toeplitz.hpp -- shared-operand batches h * r_i mod (X^n - 1) as one
+// circulant-matrix product on int8 MFMA (the circulant / ring isomorphism of
+// Section 1).  Host interface used by the C ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "gf2x.h"
+
+namespace gf2x {
+namespace toeplitz {
+
+struct Workspace {
+    void *buf = nullptr;  // device scratch: expanded operand panels
+    size_t bytes = 0;
+};
+
+// h = a_base + items[0].a_off shared by all items; r_i = b_base + items[i].b_off;
+// c_base + items[i].c_off receives h * r_i mod (X^n - 1).
+int run(Workspace &ws, size_t budget, size_t &allocated, const gf2x_item *items, uint32_t count,
+        uint64_t *c_base, const uint64_t *a_base, const uint64_t *b_base, int num_cu, hipStream_t s);
+void release(Workspace &ws);
+const char *last_error();
+
+}  // namespace toeplitz
+}  // namespace gf2x

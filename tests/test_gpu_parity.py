@@ -1,0 +1,280 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bit-exact comparison on seeded inputs: every ring size of the workloads, the
+edge sizes of the ABI, every schedule class, ragged tails, full products,
+and batched launches at full workload sizes (sampled items against the
+oracle, every item against the evaluation-at-1 invariant)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_10473_amd import gf2x, inputs
+from tests.gpu_util import empty_dev, from_dev, parity_rows, to_dev
+
+pytestmark = pytest.mark.gpu
+
+RING = inputs.RING_SIZES
+SEED = inputs.SEED_BASE
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available()
+    c = gf2x.Context(0)
+    yield c
+    c.close()
+
+
+def _single(ctx, n, a, b, kind):
+    import torch
+
+    W = oracle.words(n)
+    A, B = to_dev(a), to_dev(b)
+    C = empty_dev(W if kind == gf2x.KIND_CYCLIC else 2 * W)
+    if kind == gf2x.KIND_CYCLIC:
+        ctx.mul_cyclic(C, A, B, n)
+    else:
+        ctx.mul(C, A, B, n)
+    torch.cuda.synchronize()
+    return from_dev(C)
+
+
+@pytest.mark.parametrize("n", RING)
+def test_ring_sizes_single(ctx, n):
+    print("case ring single n=%d" % n, flush=True)
+    for item in range(3):
+        a = inputs.dense(n, SEED + 1, item, 0)
+        b = inputs.dense(n, SEED + 1, item, 1)
+        assert np.array_equal(_single(ctx, n, a, b, gf2x.KIND_CYCLIC), oracle.mul_cyclic(a, b, n))
+    assert np.array_equal(_single(ctx, n, a, b, gf2x.KIND_FULL), oracle.mul(a, b, n))
+
+
+EDGE = [1, 2, 3, 31, 32, 33, 63, 64, 65, 127, 128, 129, 255, 256, 257, 1000, 4095, 4096, 4097, 8191, 8193,
+        13311, 13313, 18239, 18241, 36095, 36097, 59137, 63743, 63745, 100000, gf2x.GF2X_MAX_BITS]
+
+
+@pytest.mark.parametrize("n", EDGE)
+def test_edge_sizes(ctx, n):
+    print("case edge n=%d" % n, flush=True)
+    a = inputs.dense(n, SEED + 2, n, 0)
+    b = inputs.dense(n, SEED + 2, n, 1)
+    assert np.array_equal(_single(ctx, n, a, b, gf2x.KIND_CYCLIC), oracle.mul_cyclic(a, b, n))
+    assert np.array_equal(_single(ctx, n, a, b, gf2x.KIND_FULL), oracle.mul(a, b, n))
+
+
+def test_degenerate_operands(ctx):
+    n = 17669
+    W = oracle.words(n)
+    zero = np.zeros(W, dtype=np.uint64)
+    ones = inputs.dense(n, 0, 0, 0) | np.uint64(0xFFFFFFFFFFFFFFFF)
+    ones[-1] &= inputs.top_mask(n)
+    one = zero.copy()
+    one[0] = 1
+    a = inputs.dense(n, SEED + 3, 0, 0)
+    for x, y in ((zero, a), (a, zero), (one, a), (ones, ones), (ones, a), (a, a)):
+        assert np.array_equal(_single(ctx, n, x, y, gf2x.KIND_CYCLIC), oracle.mul_cyclic(x, y, n))
+
+
+def test_input_bits_above_n_ignored(ctx):
+    for n in (17669, 57637, 100):
+        a = inputs.dense(n, SEED + 4, 0, 0)
+        b = inputs.dense(n, SEED + 4, 0, 1)
+        ja, jb = a.copy(), b.copy()
+        ja[-1] |= ~inputs.top_mask(n)
+        jb[-1] |= ~inputs.top_mask(n)
+        assert np.array_equal(_single(ctx, n, ja, jb, gf2x.KIND_CYCLIC), oracle.mul_cyclic(a, b, n))
+        assert np.array_equal(_single(ctx, n, ja, jb, gf2x.KIND_FULL), oracle.mul(a, b, n))
+
+
+def _class_names():
+    import ctypes
+    lib = gf2x.load()
+    seen = {}
+    # probe the default table and the tuner-visible names via schedule_info on many sizes
+    for n in range(32, gf2x.GF2X_MAX_BITS + 1, 32):
+        s = ctypes.c_uint32()
+        name = ctypes.create_string_buffer(64)
+        lib.gf2x_schedule_info(None, n, ctypes.byref(s), None, None, name, 64)
+        seen.setdefault(name.value.decode(), s.value)
+    return seen
+
+
+ALL_CLASSES = [
+    ("U4", 4), ("U8", 8), ("K2^1.U8", 16), ("K2^2.U8", 32), ("K2^3.U8", 64), ("K2^4.U8", 128),
+    ("K2^5.U8", 256), ("K2^5.U13", 416), ("T3.K2^4.U9", 426), ("T3.K2^5.U5", 474), ("T3.K2^5.U6", 570),
+    ("T3.K2^4.U12", 570), ("T3.T3.K2^5.U3", 840), ("T3.K2^5.U9", 858), ("T3.T3.K2^5.U4", 1128),
+    ("T3.T3.K2^5.U5", 1416), ("T3.T3.K2^4.U13", 1848), ("T3.T3.K2^5.U7", 1992), ("T3.T3.K2^5.U10", 2856),
+    ("T3.T3.T3.K2^5.U4", 3378), ("T3.T3.T3.K2^5.U5", 4242),
+]
+
+
+@pytest.mark.parametrize("name,S", ALL_CLASSES)
+def test_every_schedule_class(tmp_path, name, S):
+    """Force each class through a tuner table and check a full-size and a ragged n."""
+    import torch
+    ns = sorted({min(S * 32, gf2x.GF2X_MAX_BITS), max(1, min(S * 32, gf2x.GF2X_MAX_BITS) - 37)})
+    table = tmp_path / "tune.txt"
+    table.write_text("".join("%d %s\n" % ((n + 31) // 32, name) for n in ns))
+    with gf2x.Context(0, tune_cache=str(table)) as c:
+        for n in ns:
+            assert c.schedule_info(n)[3] == name
+            print("case class %s n=%d" % (name, n), flush=True)
+            a = inputs.dense(n, SEED + 5, S, 0)
+            b = inputs.dense(n, SEED + 5, S, 1)
+            assert np.array_equal(_single(c, n, a, b, gf2x.KIND_CYCLIC), oracle.mul_cyclic(a, b, n))
+            assert np.array_equal(_single(c, n, a, b, gf2x.KIND_FULL), oracle.mul(a, b, n))
+
+
+def _batched(ctx, n, count, seed, kind=gf2x.KIND_CYCLIC, flags=0, reps=1):
+    import torch
+    W = oracle.words(n)
+    A = inputs.dense_batch(n, count, seed, 0)
+    B = inputs.dense_batch(n, count, seed, 1)
+    cw = W if kind == gf2x.KIND_CYCLIC else 2 * W
+    items = gf2x.make_items(n, kind, np.arange(count) * W, np.arange(count) * W, np.arange(count) * cw)
+    dA, dB, dC = to_dev(A.ravel()), to_dev(B.ravel()), empty_dev(count * cw)
+    outs = []
+    for _ in range(reps):
+        ctx.mul_batched(items, dC, dA, dB, flags)
+        torch.cuda.synchronize()
+        outs.append(from_dev(dC).reshape(count, cw))
+    return A, B, outs
+
+
+@pytest.mark.parametrize("n", [17669, 57637])
+def test_batched_full_workload(ctx, n):
+    """4096 products in one persistent launch (the batched workload), checked:
+    32 sampled items against the oracle, every item against parity(a*b) =
+    parity(a)*parity(b)."""
+    count = 4096
+    print("case batched n=%d count=%d" % (n, count), flush=True)
+    A, B, (C,) = _batched(ctx, n, count, SEED + 2)
+    assert np.array_equal(parity_rows(C), parity_rows(A) & parity_rows(B))
+    rng = np.random.default_rng(n)
+    for i in sorted(rng.choice(count, 32, replace=False)) + [0, count - 1]:
+        assert np.array_equal(C[i], oracle.mul_cyclic(A[i], B[i], n)), i
+
+
+def test_batched_ragged_and_full_kind(ctx):
+    n = 12323
+    A, B, (C,) = _batched(ctx, n, 37, SEED + 6, kind=gf2x.KIND_FULL)
+    for i in range(37):
+        assert np.array_equal(C[i], oracle.mul(A[i], B[i], n))
+
+
+def test_batched_graph_replays(ctx):
+    n = 24659
+    A, B, outs = _batched(ctx, n, 300, SEED + 7, flags=gf2x.USE_GRAPH, reps=3)
+    for C in outs[1:]:
+        assert np.array_equal(C, outs[0])
+    for i in (0, 1, 150, 299):
+        assert np.array_equal(outs[0][i], oracle.mul_cyclic(A[i], B[i], n))
+
+
+def test_batched_device_items(ctx):
+    import torch
+    n = 35851
+    count = 50
+    W = oracle.words(n)
+    A = inputs.dense_batch(n, count, SEED + 8, 0)
+    B = inputs.dense_batch(n, count, SEED + 8, 1)
+    items = gf2x.make_items(n, gf2x.KIND_CYCLIC, np.arange(count) * W, np.arange(count) * W, np.arange(count) * W)
+    d_items = torch.from_numpy(items.view(np.uint8).copy()).cuda()
+    dA, dB, dC = to_dev(A.ravel()), to_dev(B.ravel()), empty_dev(count * W)
+    ctx.mul_batched(d_items, dC, dA, dB, gf2x.ITEMS_ON_DEVICE, count=count)
+    torch.cuda.synchronize()
+    C = from_dev(dC).reshape(count, W)
+    for i in range(0, count, 7):
+        assert np.array_equal(C[i], oracle.mul_cyclic(A[i], B[i], n))
+
+
+def test_mixed_batch_with_sparse_operands(ctx):
+    """Mixed sizes, half dense x dense and half dense x sparse, one launch.
+    Sparse items are also checked against the rotation closed form."""
+    import torch
+    from tests import brute
+    count = 96
+    rng = np.random.default_rng(4)
+    sizes = [RING[int(u)] for u in rng.integers(0, 6, count)]
+    offs, off = [], 0
+    for n in sizes:
+        offs.append(off)
+        off += oracle.words(n)
+    Abuf = np.zeros(off, dtype=np.uint64)
+    Bbuf = np.zeros(off, dtype=np.uint64)
+    sparse_pos = {}
+    for p, n in enumerate(sizes):
+        W = oracle.words(n)
+        Abuf[offs[p]:offs[p] + W] = inputs.dense(n, SEED + 4, p, 0)
+        if p % 2:
+            pos = inputs.sparse_positions(n, inputs.sparse_weight_for(n), SEED + 4, p)
+            sparse_pos[p] = pos
+            Bbuf[offs[p]:offs[p] + W] = inputs.from_positions(n, pos)
+        else:
+            Bbuf[offs[p]:offs[p] + W] = inputs.dense(n, SEED + 4, p, 1)
+    items = gf2x.make_items(sizes, gf2x.KIND_CYCLIC, offs, offs, offs)
+    dA, dB, dC = to_dev(Abuf), to_dev(Bbuf), empty_dev(off)
+    ctx.mul_batched(items, dC, dA, dB)
+    torch.cuda.synchronize()
+    C = from_dev(dC)
+    for p, n in enumerate(sizes):
+        W = oracle.words(n)
+        a, b, c = Abuf[offs[p]:offs[p] + W], Bbuf[offs[p]:offs[p] + W], C[offs[p]:offs[p] + W]
+        if p % 4 == 0 or p % 2:
+            assert np.array_equal(c, oracle.mul_cyclic(a, b, n)), p
+        if p in sparse_pos:
+            xa = brute.words_to_int(a)
+            expect = 0
+            for q in sparse_pos[p]:
+                expect ^= brute.rotate(xa, q, n)
+            assert brute.words_to_int(c) == expect
+
+
+def test_determinism_across_orders(ctx):
+    """Same products computed in a different item order and grid give identical words."""
+    import torch
+    n = 17669
+    count = 600
+    W = oracle.words(n)
+    A = inputs.dense_batch(n, count, SEED + 9, 0)
+    B = inputs.dense_batch(n, count, SEED + 9, 1)
+    dA, dB = to_dev(A.ravel()), to_dev(B.ravel())
+    perm = np.random.default_rng(1).permutation(count)
+    outs = []
+    for order in (np.arange(count), perm, perm[:7]):
+        items = gf2x.make_items(n, gf2x.KIND_CYCLIC, order * W, order * W, order * W)
+        dC = empty_dev(count * W)
+        ctx.mul_batched(items, dC, dA, dB)
+        torch.cuda.synchronize()
+        outs.append((order, from_dev(dC).reshape(count, W)))
+    base = outs[0][1]
+    for order, C in outs[1:]:
+        assert np.array_equal(C[order], base[order])
+
+
+def test_argument_errors(ctx):
+    import torch
+    n = 100
+    W = oracle.words(n)
+    A = to_dev(np.zeros(W, dtype=np.uint64))
+    C = empty_dev(2 * W)
+    with pytest.raises(gf2x.Gf2xError) as e:
+        ctx.mul_cyclic(C, A, A, 0)
+    assert e.value.code == gf2x.GF2X_EINVAL
+    with pytest.raises(gf2x.Gf2xError):
+        ctx.mul_cyclic(C, A, A, gf2x.GF2X_MAX_BITS + 1)
+    with pytest.raises(gf2x.Gf2xError):
+        ctx.mul_cyclic(A, A, C, n)  # c overlaps a
+    with pytest.raises(gf2x.Gf2xError):
+        ctx.mul_cyclic(C.data_ptr() + 4, A, A, n)  # misaligned
+    bad = gf2x.make_items(n, 7, 0, 0, 0)
+    with pytest.raises(gf2x.Gf2xError):
+        ctx.mul_batched(bad, C, A, A)
+    with pytest.raises(gf2x.Gf2xError) as e:
+        ctx.mul_batched(gf2x.make_items(n, 0, 0, 0, 0), C, A, A, gf2x.FORCE_TOEPLITZ)
+    assert e.value.code == gf2x.GF2X_ENOTSUP
+    ctx.mul_batched(np.zeros(0, dtype=gf2x.ITEM_DTYPE), C, A, A)  # empty batch is a no-op
