@@ -61,9 +61,14 @@ def time_batched(ctx, n, count, steps, warmup, seed):
     A, B, items, dA, dB, dC = make_batch(n, count, seed)
     flags = gf2x.USE_GRAPH
     stream = torch.cuda.current_stream()
-    for _ in range(max(warmup, 1)):
+    # warm-up: the requested steps, and at least ~0.5 s of device work so the
+    # engine clock has settled before the timed region
+    t0 = time.perf_counter()
+    done = 0
+    while done < max(warmup, 1) or time.perf_counter() - t0 < 0.5:
         ctx.mul_batched(items, dC, dA, dB, flags, stream)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        done += 1
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
     t0 = time.perf_counter()
     for s, e in ev:

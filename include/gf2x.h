@@ -138,6 +138,16 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count,
 int gf2x_schedule_info(gf2x_ctx *ctx, uint32_t n_bits, uint32_t *padded_words32,
                        uint64_t *base_products, uint64_t *lane_ops, char *name, size_t name_len);
 
+/* Autotuner.  For each n in sizes[0..nsizes), time every size class whose
+ * padded size holds n (up to 1.6x padding) on a batch of `batch` ring
+ * products of synthetic operands in a temporary device buffer (contents do
+ * not matter: the kernels are constant time), keep the fastest class in the
+ * context's table, and, if out_path is not NULL, write the context's tuned
+ * choices to that file ("w32 class_name" lines, the format opts->tune_cache
+ * reads).  This call is synchronous: it waits for the device on a private
+ * stream.  Errors: GF2X_EINVAL, GF2X_ENOMEM, GF2X_EDEVICE. */
+int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t batch, const char *out_path);
+
 /* Static message for a GF2X_E* code. */
 const char *gf2x_strerror(int code);
 

@@ -61,6 +61,7 @@ struct gf2x_ctx {
              GraphEntry>
         graphs;
     toeplitz::Workspace tz;
+    std::map<uint32_t, int> tuned;  // w32 -> class chosen by gf2x_tune or the cache file
 };
 
 namespace {
@@ -96,8 +97,10 @@ int load_tune_cache(gf2x_ctx *ctx, const char *path) {
         if (line[0] == '#' || std::sscanf(line, "%u %127s", &w, name) != 2) continue;
         if (w == 0 || w > kMaxWords32) continue;
         for (int c = 0; c < kNumClasses; ++c)
-            if (std::strcmp(class_info(c).name, name) == 0 && (uint32_t)class_info(c).S >= w)
+            if (std::strcmp(class_info(c).name, name) == 0 && (uint32_t)class_info(c).S >= w) {
                 ctx->cls_of_w32[w] = c;
+                ctx->tuned[w] = c;
+            }
     }
     std::fclose(f);
     return GF2X_OK;
@@ -365,6 +368,80 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
     if (rc) return rc;
     HIP_TRY(hipEventRecord(ctx->ws_free, s));
     ctx->ws_used = true;
+    return GF2X_OK;
+}
+
+int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t batch, const char *out_path) {
+    if (!ctx || (!sizes && nsizes) || batch == 0) return GF2X_EINVAL;
+    for (uint32_t i = 0; i < nsizes; ++i)
+        if (sizes[i] == 0 || sizes[i] > kMaxBits) return GF2X_EINVAL;
+    HIP_TRY(hipSetDevice(ctx->device));
+    uint32_t maxn = 0;
+    for (uint32_t i = 0; i < nsizes; ++i) maxn = std::max(maxn, sizes[i]);
+    if (nsizes) {
+        const uint64_t W = words64(maxn);
+        const size_t bytes = (size_t)batch * W * 8 * 3 + (size_t)batch * sizeof(DevItem);
+        if (ctx->allocated + bytes > ctx->budget) return GF2X_ENOMEM;
+        uint64_t *buf = nullptr;
+        if (hipMalloc(&buf, bytes) != hipSuccess) return GF2X_ENOMEM;
+        hipStream_t s = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e == hipSuccess) e = launch_fill_words(buf, (size_t)batch * W * 2, 0x2201047300ull, s);
+        uint64_t *A = buf, *B = buf + (size_t)batch * W, *C = buf + (size_t)2 * batch * W;
+        DevItem *d_items = reinterpret_cast<DevItem *>(buf + (size_t)3 * batch * W);
+        std::vector<DevItem> host(batch);
+        for (uint32_t i = 0; e == hipSuccess && i < nsizes; ++i) {
+            const uint32_t n = sizes[i], w32 = (n + 31u) / 32u;
+            const uint64_t Wn = words64(n);
+            for (uint32_t k = 0; k < batch; ++k) host[k] = DevItem{n, kKindCyclic, 0u, 0u, k * Wn, k * Wn, k * Wn};
+            e = hipMemcpyAsync(d_items, host.data(), batch * sizeof(DevItem), hipMemcpyHostToDevice, s);
+            int best = -1;
+            float best_ms = 0.f;
+            for (int c = 0; e == hipSuccess && c < kNumClasses; ++c) {
+                const ClassInfo &ci = class_info(c);
+                if ((uint32_t)ci.S < w32 || (double)ci.S > 1.6 * w32 + 8) continue;
+                float t = 0.f;
+                for (int rep = 0; e == hipSuccess && rep < 4; ++rep) {
+                    e = hipEventRecord(e0, s);
+                    if (e == hipSuccess) e = launch_batched(c, d_items, batch, C, A, B, ctx->num_cu, s);
+                    if (e == hipSuccess) e = hipEventRecord(e1, s);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    float ms = 0.f;
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    if (rep == 1 || (rep > 1 && ms < t)) t = ms;  // rep 0 is a warm-up
+                }
+                if (e == hipSuccess && (best < 0 || t < best_ms)) {
+                    best = c;
+                    best_ms = t;
+                }
+            }
+            if (e == hipSuccess && best >= 0) {
+                ctx->cls_of_w32[w32] = best;
+                ctx->tuned[w32] = best;
+            }
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e == hipSuccess) {
+            uint8_t tab[kMaxWords32 + 1];
+            for (uint32_t w = 0; w <= kMaxWords32; ++w) tab[w] = (uint8_t)ctx->cls_of_w32[w];
+            e = hipMemcpy(ctx->d_cls, tab, sizeof tab, hipMemcpyHostToDevice);
+        }
+        if (e0) hipEventDestroy(e0);
+        if (e1) hipEventDestroy(e1);
+        if (s) hipStreamDestroy(s);
+        hipFree(buf);
+        if (e != hipSuccess) return device_error(e);
+    }
+    if (out_path) {
+        FILE *f = std::fopen(out_path, "w");
+        if (!f) return GF2X_EINVAL;
+        std::fprintf(f, "# gf2x schedule table: <ceil(n/32)> <class name>, written by gf2x_tune\n");
+        for (auto &kv : ctx->tuned) std::fprintf(f, "%u %s\n", kv.first, class_info(kv.second).name);
+        std::fclose(f);
+    }
     return GF2X_OK;
 }
 

@@ -50,6 +50,26 @@ __device__ __forceinline__ u32 funnel(u32 hi, u32 lo, u32 s) {
     return __builtin_amdgcn_alignbit(hi, lo, s);
 }
 
+// dst[idx] = f(idx) for 0 <= idx < TOTAL, spread over the workgroup.  Each
+// thread computes all of its values before it stores any, so its loads are
+// issued back to back and the pass costs one memory round trip, not one per
+// element.  f may read dst only at its own idx.
+template <int TOTAL, class F>
+__device__ __forceinline__ void par_map(u32 *dst, F f) {
+    constexpr int IT = (TOTAL + NT - 1) / NT;
+    u32 v[IT];
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int idx = threadIdx.x + i * NT;
+        if (IT * NT == TOTAL || idx < TOTAL) v[i] = f(idx);
+    }
+#pragma unroll
+    for (int i = 0; i < IT; ++i) {
+        const int idx = threadIdx.x + i * NT;
+        if (IT * NT == TOTAL || idx < TOTAL) dst[idx] = v[i];
+    }
+}
+
 // ------------------------------------------------------------------ base case
 // c (2T words) = a (T words) * b (T words) in F2[X], all in registers.
 //
@@ -308,22 +328,20 @@ struct SeqT3 {
     // Operands of point e (0: 0, 1: 1, 2: x, 3: x+1, 4: inf) into cin.
     template <int E>
     __device__ static void eval(const u32 *A, u32 *cin) {
-        for (int idx = threadIdx.x; idx < 2 * S1; idx += NT) {
+        par_map<2 * S1>(cin, [&](int idx) -> u32 {
             const int x = idx / S1;
             const int w = idx - x * S1;
             const u32 *p = A + x * S;  // [a | b] layout, each S words
             auto get = [&](int part, int j) -> u32 {
                 return (j >= 0 && j < m) ? p[part * m + j] : 0u;
             };
-            u32 v;
-            if constexpr (E == 0) v = get(0, w);
-            else if constexpr (E == 1) v = get(0, w) ^ get(1, w) ^ get(2, w);
-            else if constexpr (E == 2) v = get(0, w) ^ get(1, w - 1) ^ get(2, w - 2);
+            if constexpr (E == 0) return get(0, w);
+            else if constexpr (E == 1) return get(0, w) ^ get(1, w) ^ get(2, w);
+            else if constexpr (E == 2) return get(0, w) ^ get(1, w - 1) ^ get(2, w - 2);
             else if constexpr (E == 3)
-                v = get(0, w) ^ get(1, w) ^ get(2, w) ^ get(1, w - 1) ^ get(2, w - 2);
-            else v = get(2, w);
-            cin[idx] = v;
-        }
+                return get(0, w) ^ get(1, w) ^ get(2, w) ^ get(1, w - 1) ^ get(2, w - 2);
+            else return get(2, w);
+        });
     }
 
     // Fold point product p (2*S1 words) into R and the numerators Sa, Ua.
@@ -331,26 +349,20 @@ struct SeqT3 {
     __device__ static void absorb(const u32 *p, u32 *R, u32 *Sa, u32 *Ua) {
         auto P = [&](int j) -> u32 { return (j >= 0 && j < 2 * S1) ? p[j] : 0u; };
         if constexpr (E == 0 || E == 1 || E == 4) {
-            for (int r = threadIdx.x; r < R_WORDS; r += NT) {
-                u32 v;
-                if constexpr (E == 0) v = P(r) ^ P(r - m);
-                else if constexpr (E == 1) v = P(r - m);
-                else v = P(r - m) ^ P(r - 4 * m);
-                R[r] ^= v;
-            }
+            par_map<R_WORDS>(R, [&](int r) -> u32 {
+                if constexpr (E == 0) return R[r] ^ P(r) ^ P(r - m);
+                else if constexpr (E == 1) return R[r] ^ P(r - m);
+                else return R[r] ^ P(r - m) ^ P(r - 4 * m);
+            });
         }
-        if constexpr (E != 4) {
-            for (int k = threadIdx.x; k < 2 * S1; k += NT) Sa[k] ^= p[k];
-        }
+        if constexpr (E != 4) par_map<2 * S1>(Sa, [&](int k) -> u32 { return Sa[k] ^ p[k]; });
         if constexpr (E != 0) {
-            for (int k = threadIdx.x; k < UA_WORDS; k += NT) {
-                u32 v;
-                if constexpr (E == 1) v = P(k);
-                else if constexpr (E == 2) v = P(k - 1);
-                else if constexpr (E == 3) v = P(k) ^ P(k - 1);
-                else v = P(k - 1) ^ P(k - 4);
-                Ua[k] ^= v;
-            }
+            par_map<UA_WORDS>(Ua, [&](int k) -> u32 {
+                if constexpr (E == 1) return Ua[k] ^ P(k);
+                else if constexpr (E == 2) return Ua[k] ^ P(k - 1);
+                else if constexpr (E == 3) return Ua[k] ^ P(k) ^ P(k - 1);
+                else return Ua[k] ^ P(k - 1) ^ P(k - 4);
+            });
         }
     }
 
@@ -379,11 +391,9 @@ struct SeqT3 {
         point<3>(in, R, Sa, Ua, cin, cs);
         point<4>(in, R, Sa, Ua, cin, cs);
         div_xx1_pair<2 * m>(Sa, Ua, tmp);  // Sa <- c3, Ua <- c2 (first 2m words)
-        for (int r = threadIdx.x; r < R_WORDS; r += NT) {
-            auto c3 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Sa[j] : 0u; };
-            auto c2 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Ua[j] : 0u; };
-            R[r] ^= c2(r - m) ^ c2(r - 2 * m) ^ c3(r - m) ^ c3(r - 3 * m);
-        }
+        auto c3 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Sa[j] : 0u; };
+        auto c2 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Ua[j] : 0u; };
+        par_map<R_WORDS>(R, [&](int r) -> u32 { return R[r] ^ c2(r - m) ^ c2(r - 2 * m) ^ c3(r - m) ^ c3(r - 3 * m); });
         __syncthreads();
         return R;
     }

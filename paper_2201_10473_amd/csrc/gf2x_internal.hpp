@@ -39,6 +39,7 @@ hipError_t launch_single(int cls, const uint64_t *a, const uint64_t *b, uint64_t
                          hipStream_t s);
 hipError_t launch_batched(int cls, const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
                           const uint64_t *b_base, int num_cu, hipStream_t s);
+hipError_t launch_fill_words(uint64_t *dst, size_t count, uint64_t seed, hipStream_t s);
 hipError_t launch_convert_items(const struct gf2x_item *items, uint32_t count, DevItem *out, hipStream_t s);
 hipError_t launch_mixed(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
                         const uint64_t *b_base, const uint8_t *cls_of_w32, bool use_table, int lds_bytes,

@@ -57,6 +57,16 @@ __global__ void k_convert_items(const gf2x_item *items, u32 count, DevItem *out)
     }
 }
 
+// Pseudo-random words for timing runs (SplitMix64 finaliser of seed + index).
+__global__ void k_fill_words(uint64_t *dst, size_t count, uint64_t seed) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+        uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        dst[i] = z ^ (z >> 31);
+    }
+}
+
 // ------------------------------------------------------------ host side
 #define GF2X_INFO(id, name, T) \
     {id, name, T::S, lds_words<T>() * 4, T::BASE, T::OPS},
@@ -108,6 +118,11 @@ hipError_t launch_batched(int cls, const DevItem *items, uint32_t count, uint64_
     const uint32_t grid = (uint32_t)(count < cap ? count : cap);
     BatchedFn fn = reinterpret_cast<BatchedFn>(const_cast<void *>(fnp));
     hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, s, items, count, c_base, a_base, b_base);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_words(uint64_t *dst, size_t count, uint64_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_words, dim3(1024), dim3(256), 0, s, dst, count, seed);
     return hipGetLastError();
 }
 

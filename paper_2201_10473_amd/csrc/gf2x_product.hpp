@@ -91,19 +91,12 @@ __device__ __forceinline__ void stage(const uint64_t *a, const uint64_t *b, u32 
     const int w32 = (int)((n + 31u) / 32u);
     const u32 s = n % 32u;
     const u32 top = s ? ((1u << s) - 1u) : 0xFFFFFFFFu;
-    for (int k = threadIdx.x; k < S; k += NT) {
-        u32 x = 0, y = 0;
-        if (k < w32) {
-            x = load_word32(a, k);
-            y = load_word32(b, k);
-            if (k == w32 - 1) {
-                x &= top;
-                y &= top;
-            }
-        }
-        smem[k] = x;
-        smem[S + k] = y;
-    }
+    auto word = [&](const uint64_t *src, int k) -> u32 {
+        if (k >= w32) return 0u;
+        const u32 x = load_word32(src, k);
+        return k == w32 - 1 ? (x & top) : x;
+    };
+    par_map<2 * S>(smem, [&](int idx) -> u32 { return idx < S ? word(a, idx) : word(b, idx - S); });
 }
 
 // Ring product epilogue: out32[k] = R[k] ^ (R >> n)[k] for k < ceil(n/32),

@@ -13,6 +13,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgf2x.so")
+# Schedule table measured on MI355X by ``python -m paper_2201_10473_amd.tune``.
+DEFAULT_TUNE_CACHE = os.path.join(_HERE, "tune_gfx950.txt")
 
 GF2X_OK = 0
 GF2X_EINVAL = -1
@@ -82,6 +84,8 @@ def load():
         vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.c_char_p, sz
     ]
     lib.gf2x_schedule_info.restype = ctypes.c_int
+    lib.gf2x_tune.argtypes = [vp, ctypes.POINTER(u32), u32, u32, ctypes.c_char_p]
+    lib.gf2x_tune.restype = ctypes.c_int
     lib.gf2x_strerror.argtypes = [ctypes.c_int]
     lib.gf2x_strerror.restype = ctypes.c_char_p
     lib.gf2x_last_device_error.argtypes = []
@@ -123,8 +127,12 @@ def _check(rc, where):
 class Context:
     """A library context bound to one HIP device."""
 
-    def __init__(self, device=0, hbm_budget_bytes=0, tune_cache=None):
+    def __init__(self, device=0, hbm_budget_bytes=0, tune_cache="default"):
+        """tune_cache: path of a schedule table, "default" for the packaged
+        MI355X table (if present), or None for the built-in cost model."""
         lib = load()
+        if tune_cache == "default":
+            tune_cache = DEFAULT_TUNE_CACHE if os.path.exists(DEFAULT_TUNE_CACHE) else None
         self._lib = lib
         opts = _Opts(device, hbm_budget_bytes, tune_cache.encode() if tune_cache else None, 0)
         h = ctypes.c_void_p()
@@ -176,6 +184,14 @@ class Context:
                 _stream(stream),
             ),
             "gf2x_mul_batched",
+        )
+
+    def tune(self, sizes, batch=4096, out_path=None):
+        """Measure every candidate schedule for each size; keep the fastest."""
+        arr = (ctypes.c_uint32 * len(sizes))(*[int(x) for x in sizes])
+        _check(
+            self._lib.gf2x_tune(self._h, arr, len(sizes), int(batch), out_path.encode() if out_path else None),
+            "gf2x_tune",
         )
 
     def schedule_info(self, n):

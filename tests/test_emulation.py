@@ -1,0 +1,57 @@
+"""The device algorithm of every schedule class, run on the CPU.
+
+The library's device headers are compiled with g++ behind a stand-in
+hip/hip_runtime.h (tests/emu): one workgroup is NT host threads with a
+pthread barrier for __syncthreads.  Products are compared bit for bit with
+the oracle.  This checks the Karatsuba / Toom-3 bookkeeping, the fold and
+the staging logic without a GPU (it does not check gfx950 code generation,
+which the GPU tests do)."""
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_10473_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def emu(tmp_path_factory):
+    so = str(tmp_path_factory.mktemp("emu") / "libemu.so")
+    subprocess.check_call(
+        ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wno-unknown-pragmas",
+         "-I", os.path.join(ROOT, "tests", "emu"), "-I", os.path.join(ROOT, "include"),
+         "-I", os.path.join(ROOT, "paper_2201_10473_amd", "csrc"),
+         os.path.join(ROOT, "tests", "emu", "emu.cpp"), "-o", so]
+    )
+    lib = ctypes.CDLL(so)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.emu_mul.argtypes = [ctypes.c_int, u64p, u64p, u64p, ctypes.c_uint32, ctypes.c_uint32]
+    lib.emu_class_words.argtypes = [ctypes.c_int]
+    return lib
+
+
+def _run(lib, cls, n, seed):
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    a = inputs.dense(n, seed, cls, 0)
+    b = inputs.dense(n, seed, cls, 1)
+    W = oracle.words(n)
+    c = np.zeros(W, dtype=np.uint64)
+    f = np.zeros(2 * W, dtype=np.uint64)
+    lib.emu_mul(cls, a.ctypes.data_as(u64p), b.ctypes.data_as(u64p), c.ctypes.data_as(u64p), n, 0)
+    lib.emu_mul(cls, a.ctypes.data_as(u64p), b.ctypes.data_as(u64p), f.ctypes.data_as(u64p), n, 1)
+    assert np.array_equal(c, oracle.mul_cyclic(a, b, n)), (cls, n)
+    assert np.array_equal(f, oracle.mul(a, b, n)), (cls, n)
+
+
+# classes 19 and 20 (three Toom-3 levels) take ~15 s each on the CPU and are
+# covered on the GPU by test_every_schedule_class
+@pytest.mark.parametrize("cls", range(19))
+def test_class_full_and_ragged(emu, cls):
+    S = emu.emu_class_words(cls)
+    for n in sorted({S * 32, max(1, S * 32 - 37)}):
+        _run(emu, cls, n, 12)
