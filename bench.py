@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "products/sec at n=17669 & 57637 (batched vs one-per-launch); % int-op roofline"
 VALU_PEAK = 256 * 64 * 2.4e9  # int32 lane-ops per second
+INT8_PEAK = 5.0e15  # dense int8 matrix ops per second (2 per multiply-add)
 BATCH = 4096
 
 
@@ -101,6 +102,36 @@ def time_one_per_launch(ctx, n, count, seed):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return {"A": A, "B": B, "C": dC, "wall_s": wall}
+
+
+def time_shared(ctx, n, count, flags, steps, seed):
+    """Shared-operand batch (one h, `count` vectors r_i) through the path pinned by flags."""
+    import numpy as np
+    import torch
+
+    from paper_2201_10473_amd import gf2x, inputs
+
+    W = gf2x.words(n)
+    h = inputs.dense(n, seed, 0, 0)
+    R = inputs.dense_batch(n, count, seed, 1)
+    items = gf2x.make_items(n, gf2x.KIND_CYCLIC, 0, np.arange(count) * W, np.arange(count) * W)
+    dH = torch.from_numpy(h.view(np.int64)).cuda()
+    dR = torch.from_numpy(R.ravel().view(np.int64)).cuda()
+    dC = torch.zeros(count * W, dtype=torch.int64, device="cuda")
+    f = gf2x.SHARED_A | flags
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.3:
+        ctx.mul_batched(items, dC, dH, dR, f)
+        torch.cuda.synchronize()
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s_ev.record()
+    for _ in range(steps):
+        ctx.mul_batched(items, dC, dH, dR, f)
+    e_ev.record()
+    torch.cuda.synchronize()
+    ms = s_ev.elapsed_time(e_ev) / steps
+    C = dC.cpu().numpy().view(np.uint64).reshape(count, W)
+    return ms, h, R, C
 
 
 def check_sample(res, n, count, k=6):
@@ -230,6 +261,31 @@ def main():
         results[n] = res
         log("n=%d: %.0f products/s, launch %.3f ms, VALU frac %.3f" % (n, res["products_per_s"], res["launch_ms"], res["valu_frac"]))
 
+    shared = {}
+    if not args.only_n:
+        import numpy as np
+
+        import oracle
+
+        for n, count in ((35851, 1024), (57637, 512)):
+            log("shared-operand n=%d x %d: packed vs Toeplitz int8 MFMA" % (n, count))
+            ms_p, h, R, Cp = time_shared(ctx, n, count, gf2x.FORCE_PACKED, 10, seed + 1)
+            ms_t, _, _, Ct = time_shared(ctx, n, count, gf2x.FORCE_TOEPLITZ, 10, seed + 1)
+            if not np.array_equal(Cp, Ct):
+                raise AssertionError("Toeplitz and packed paths disagree at n=%d" % n)
+            for i in (0, count - 1):
+                if not np.array_equal(Ct[i], oracle.mul_cyclic(h, R[i], n)):
+                    raise AssertionError("shared-operand item %d differs from the oracle" % i)
+            macs = float(n) * n * count  # one int8 multiply-add per matrix entry
+            shared[str(n)] = {
+                "batch": count,
+                "packed_products_per_s": round(count / (ms_p * 1e-3), 1),
+                "toeplitz_products_per_s": round(count / (ms_t * 1e-3), 1),
+                "toeplitz_over_packed": round(ms_p / ms_t, 4),
+                "toeplitz_mfma_frac": round(2 * macs / (ms_t * 1e-3) / INT8_PEAK, 4),
+            }
+            log("  packed %.3f ms, toeplitz %.3f ms" % (ms_p, ms_t))
+
     head = sizes[0]
     main_res = results[head]
     achieved = main_res["lane_ops_per_product"] * BATCH / (main_res["launch_ms"] * 1e-3)
@@ -264,8 +320,11 @@ def main():
             "schedule": main_res["schedule"],
         },
         "roofline": roof,
-        "extra": {str(n): {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
-                  for n, r in results.items()},
+        "extra": dict(
+            {str(n): {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
+             for n, r in results.items()},
+            shared_operand=shared,
+        ),
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) n=%d" % head)

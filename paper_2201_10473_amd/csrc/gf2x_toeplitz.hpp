@@ -13,9 +13,18 @@ namespace gf2x {
 namespace toeplitz {
 
 struct Workspace {
-    void *buf = nullptr;  // device scratch: expanded operand panels
+    void *buf = nullptr;       // device scratch: bit image of h and item offsets
     size_t bytes = 0;
+    hipEvent_t done = nullptr; // recorded after the last launch that read buf
+    bool used = false;
 };
+
+// Shape constants shared with the host driver.
+constexpr int kRowsWG = 256;    // output bits per workgroup
+constexpr int kColsWG = 64;     // batch items per workgroup
+constexpr int kStepBits = 128;  // K bits per step
+constexpr int kColStride = 36;  // dwords per item row of the spread tile (32 + pad)
+constexpr int kTileDwords = kColsWG * kColStride;
 
 // h = a_base + items[0].a_off shared by all items; r_i = b_base + items[i].b_off;
 // c_base + items[i].c_off receives h * r_i mod (X^n - 1).

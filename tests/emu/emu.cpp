@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "gf2x_product.hpp"
+#include "gf2x_toeplitz_device.hpp"
 
 thread_local EmuIdx threadIdx;
 
@@ -25,6 +26,40 @@ unsigned __shfl_up(unsigned v, int delta, int width) {
     const unsigned r = lane >= (unsigned)delta ? g_xch[t - delta] : v;
     pthread_barrier_wait(&g_bar);
     return r;
+}
+
+unsigned __shfl_xor(unsigned v, int mask, int width) {
+    const unsigned t = threadIdx.x;
+    g_xch[t] = v;
+    pthread_barrier_wait(&g_bar);
+    const unsigned base = t - t % (unsigned)width;
+    const unsigned r = g_xch[base + ((t % (unsigned)width) ^ (unsigned)mask)];
+    pthread_barrier_wait(&g_bar);
+    return r;
+}
+
+static emu_v4i g_ma[gf2x::NT], g_mb[gf2x::NT];
+
+emu_v4i emu_mfma_i32_16x16x64_i8(emu_v4i a, emu_v4i b, emu_v4i c) {
+    const unsigned t = threadIdx.x;
+    g_ma[t] = a;
+    g_mb[t] = b;
+    pthread_barrier_wait(&g_bar);
+    const unsigned w = t - t % 64u, l = t % 64u;
+    emu_v4i out = c;
+    for (int r = 0; r < 4; ++r) {
+        const unsigned row = 4 * (l / 16) + r, col = l % 16;
+        int sum = 0;
+        for (int k = 0; k < 64; ++k) {
+            emu_v4i av = g_ma[w + row + 16 * (k / 16)], bv = g_mb[w + col + 16 * (k / 16)];
+            const int8_t *ab = reinterpret_cast<const int8_t *>(&av);
+            const int8_t *bb = reinterpret_cast<const int8_t *>(&bv);
+            sum += (int)ab[k % 16] * (int)bb[k % 16];
+        }
+        out[r] += sum;
+    }
+    pthread_barrier_wait(&g_bar);
+    return out;
 }
 
 namespace {
@@ -77,5 +112,56 @@ extern "C" int emu_mul(int cls, const uint64_t *a, const uint64_t *b, uint64_t *
     }
     for (int t = 0; t < gf2x::NT; ++t) pthread_join(th[t], nullptr);
     pthread_barrier_destroy(&g_bar);
+    return 0;
+}
+
+// Shared-operand batch through the Toeplitz tiles: h (W words), R (count x W),
+// C (count x W) = h * r_i mod (X^n - 1).  Mirrors the host driver's sizing.
+namespace {
+struct TzJob {
+    const uint32_t *hr;
+    uint32_t hr_dwords, n, P, count, bx, by;
+    const uint64_t *R, *boff;
+    uint64_t *C;
+    const uint64_t *coff;
+    uint32_t *lds;
+    unsigned tid;
+};
+void *tz_worker(void *p) {
+    TzJob *j = static_cast<TzJob *>(p);
+    threadIdx.x = j->tid;
+    gf2x::toeplitz::toeplitz_tile(j->hr, j->hr_dwords, j->n, j->P, j->R, j->boff, j->C, j->coff, j->count, j->bx,
+                                  j->by, j->lds);
+    return nullptr;
+}
+}  // namespace
+
+extern "C" int emu_toeplitz(const uint64_t *h, uint32_t n, const uint64_t *R, uint64_t *C, uint32_t count) {
+    using namespace gf2x::toeplitz;
+    const uint32_t W = (n + 63) / 64;
+    const uint32_t steps = (n + kStepBits - 1) / kStepBits;
+    const uint32_t rows = (n + kRowsWG - 1) / kRowsWG * kRowsWG;
+    const uint32_t P = rows + 64;
+    const uint32_t hr_dwords = (P + steps * kStepBits + 128 + 31) / 32 + 2;
+    std::vector<uint32_t> hr(hr_dwords);
+    for (uint32_t d = 0; d < hr_dwords; ++d) hr[d] = hr_dword(h, n, P, d);
+    std::vector<uint64_t> boff(count), coff(count);
+    for (uint32_t i = 0; i < count; ++i) boff[i] = coff[i] = (uint64_t)i * W;
+    const uint32_t hr_len_max = (kRowsWG + kStepBits * steps + 96 + 64) / 32 + 4;
+    const size_t lds_words = ((hr_len_max + 3) & ~3u) + 2 * kTileDwords;
+    for (uint32_t bx = 0; bx < rows / kRowsWG; ++bx)
+        for (uint32_t by = 0; by < (count + kColsWG - 1) / kColsWG; ++by) {
+            std::vector<uint32_t> lds(lds_words, 0xDEADBEEFu);
+            pthread_barrier_init(&g_bar, nullptr, gf2x::NT);
+            std::vector<pthread_t> th(gf2x::NT);
+            std::vector<TzJob> jobs(gf2x::NT);
+            for (int t = 0; t < gf2x::NT; ++t) {
+                jobs[t] = TzJob{hr.data(), hr_dwords, n, P, count, bx, by, R, boff.data(), C, coff.data(),
+                                lds.data(), (unsigned)t};
+                pthread_create(&th[t], nullptr, tz_worker, &jobs[t]);
+            }
+            for (int t = 0; t < gf2x::NT; ++t) pthread_join(th[t], nullptr);
+            pthread_barrier_destroy(&g_bar);
+        }
     return 0;
 }

@@ -16,6 +16,7 @@
 
 typedef int hipError_t;
 typedef struct ihipStream_t *hipStream_t;
+typedef struct ihipEvent_t *hipEvent_t;
 
 struct EmuIdx {
     unsigned x, y, z;
@@ -24,6 +25,15 @@ extern thread_local EmuIdx threadIdx;
 
 void __syncthreads();
 unsigned __shfl_up(unsigned v, int delta, int width);
+unsigned __shfl_xor(unsigned v, int mask, int width);
+
+// v_mfma_i32_16x16x64_i8 for one wave of 64 emulated lanes (all lanes of the
+// workgroup reach every call): lane l supplies A[l%16][16*(l/16) + byte],
+// B[16*(l/16) + byte][l%16] and receives C[4*(l/16) + r][l%16] -- the layout
+// measured on gfx950.
+typedef int emu_v4i __attribute__((ext_vector_type(4)));
+emu_v4i emu_mfma_i32_16x16x64_i8(emu_v4i a, emu_v4i b, emu_v4i c);
+#define __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, x, y, z) emu_mfma_i32_16x16x64_i8((a), (b), (c))
 
 // v_bitop3_b32: bit k of the result is bit (4*S0_k + 2*S1_k + S2_k) of imm.
 static inline uint32_t emu_bitop3(uint32_t s0, uint32_t s1, uint32_t s2, unsigned imm) {

@@ -23,7 +23,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def emu(tmp_path_factory):
     so = str(tmp_path_factory.mktemp("emu") / "libemu.so")
     subprocess.check_call(
-        ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wno-unknown-pragmas",
+        ["/opt/rocm/llvm/bin/clang++", "-O2", "-std=c++17", "-fPIC", "-shared", "-pthread", "-Wno-unknown-pragmas",
          "-I", os.path.join(ROOT, "tests", "emu"), "-I", os.path.join(ROOT, "include"),
          "-I", os.path.join(ROOT, "paper_2201_10473_amd", "csrc"),
          os.path.join(ROOT, "tests", "emu", "emu.cpp"), "-o", so]
@@ -32,6 +32,7 @@ def emu(tmp_path_factory):
     u64p = ctypes.POINTER(ctypes.c_uint64)
     lib.emu_mul.argtypes = [ctypes.c_int, u64p, u64p, u64p, ctypes.c_uint32, ctypes.c_uint32]
     lib.emu_class_words.argtypes = [ctypes.c_int]
+    lib.emu_toeplitz.argtypes = [u64p, ctypes.c_uint32, u64p, u64p, ctypes.c_uint32]
     return lib
 
 
@@ -55,3 +56,19 @@ def test_class_full_and_ragged(emu, cls):
     S = emu.emu_class_words(cls)
     for n in sorted({S * 32, max(1, S * 32 - 37)}):
         _run(emu, cls, n, 12)
+
+
+@pytest.mark.parametrize("n,count", [(1, 3), (37, 5), (127, 70), (300, 9), (700, 3)])
+def test_toeplitz_tile(emu, n, count):
+    """The shared-operand MFMA tile with an emulated 16x16x64 int8 matrix
+    instruction (layout as measured on gfx950); bits above n are ignored."""
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    W = oracle.words(n)
+    h = inputs.dense(n, 3, n, 0)
+    R = inputs.dense_batch(n, count, 3, 1)
+    R[:, -1] |= ~inputs.top_mask(n)
+    C = np.full((count, W), 0x5A5A5A5A5A5A5A5A, dtype=np.uint64)
+    emu.emu_toeplitz(h.ctypes.data_as(u64p), n, R.ctypes.data_as(u64p), C.ctypes.data_as(u64p), count)
+    R[:, -1] &= inputs.top_mask(n)
+    for i in range(count):
+        assert np.array_equal(C[i], oracle.mul_cyclic(h, R[i], n)), i

@@ -256,6 +256,58 @@ def test_determinism_across_orders(ctx):
         assert np.array_equal(C[order], base[order])
 
 
+def _shared(ctx, n, count, seed, flags):
+    import torch
+    W = oracle.words(n)
+    h = inputs.dense(n, seed, 0, 0)
+    R = inputs.dense_batch(n, count, seed, 1)
+    items = gf2x.make_items(n, gf2x.KIND_CYCLIC, 0, np.arange(count) * W, np.arange(count) * W)
+    dH, dR, dC = to_dev(h), to_dev(R.ravel()), empty_dev(count * W)
+    ctx.mul_batched(items, dC, dH, dR, gf2x.SHARED_A | flags)
+    torch.cuda.synchronize()
+    return h, R, from_dev(dC).reshape(count, W)
+
+
+@pytest.mark.parametrize("n,count", [(35851, 1024), (57637, 512)])
+def test_shared_operand_toeplitz_and_packed(ctx, n, count):
+    """The shared-operand workload through the int8-MFMA Toeplitz path and the
+    bit-packed path: identical words, sampled items equal to the oracle, every
+    item satisfies the evaluation-at-1 invariant."""
+    print("case shared n=%d count=%d" % (n, count), flush=True)
+    h, R, Ct = _shared(ctx, n, count, SEED + 3, gf2x.FORCE_TOEPLITZ)
+    _, _, Cp = _shared(ctx, n, count, SEED + 3, gf2x.FORCE_PACKED)
+    assert np.array_equal(Ct, Cp)
+    ph = parity_rows(h[None, :])[0]
+    assert np.array_equal(parity_rows(Ct), parity_rows(R) & ph)
+    for i in sorted(set(np.linspace(0, count - 1, 12).astype(int))):
+        assert np.array_equal(Ct[i], oracle.mul_cyclic(h, R[i], n)), i
+
+
+@pytest.mark.parametrize("n,count", [(1, 5), (63, 3), (64, 64), (65, 65), (1000, 130), (12323, 7), (17669, 100)])
+def test_toeplitz_ragged(ctx, n, count):
+    h, R, C = _shared(ctx, n, count, SEED + 5, gf2x.FORCE_TOEPLITZ)
+    for i in range(count):
+        assert np.array_equal(C[i], oracle.mul_cyclic(h, R[i], n)), i
+
+
+def test_toeplitz_ignores_bits_above_n(ctx):
+    import torch
+    n, count = 17669, 70
+    W = oracle.words(n)
+    h = inputs.dense(n, SEED + 6, 0, 0)
+    R = inputs.dense_batch(n, count, SEED + 6, 1)
+    hj, Rj = h.copy(), R.copy()
+    hj[-1] |= ~inputs.top_mask(n)
+    Rj[:, -1] |= ~inputs.top_mask(n)
+    items = gf2x.make_items(n, gf2x.KIND_CYCLIC, 0, np.arange(count) * W, np.arange(count) * W)
+    dC = empty_dev(count * W)
+    ctx.mul_batched(items, dC, to_dev(hj), to_dev(Rj.ravel()), gf2x.SHARED_A | gf2x.FORCE_TOEPLITZ)
+    torch.cuda.synchronize()
+    C = from_dev(dC).reshape(count, W)
+    for i in (0, 33, 69):
+        assert np.array_equal(C[i], oracle.mul_cyclic(h, R[i], n))
+
+
 def test_argument_errors(ctx):
     import torch
     n = 100
@@ -277,4 +329,8 @@ def test_argument_errors(ctx):
     with pytest.raises(gf2x.Gf2xError) as e:
         ctx.mul_batched(gf2x.make_items(n, 0, 0, 0, 0), C, A, A, gf2x.FORCE_TOEPLITZ)
     assert e.value.code == gf2x.GF2X_ENOTSUP
+    two = gf2x.make_items(n, 0, [0, 1], 0, 0)  # SHARED_A with different a_off
+    with pytest.raises(gf2x.Gf2xError) as e:
+        ctx.mul_batched(two, C, A, A, gf2x.SHARED_A)
+    assert e.value.code == gf2x.GF2X_EINVAL
     ctx.mul_batched(np.zeros(0, dtype=gf2x.ITEM_DTYPE), C, A, A)  # empty batch is a no-op
