@@ -114,23 +114,20 @@ __device__ __forceinline__ void unit_mul(const u32 (&a)[T], const u32 (&b)[T], u
     }
 }
 
-// One thread per unit: unit u's operands [a_u | b_u] (2T words) sit at
-// P + 2T*u; its 2T-word product overwrites them.
-template <int T, int UNITS>
-__device__ __forceinline__ void run_units(u32 *P) {
-    for (int u = threadIdx.x; u < UNITS; u += NT) {
-        u32 *p = P + 2 * T * u;
-        u32 a[T], b[T], c[2 * T];
-#pragma unroll
-        for (int k = 0; k < T; ++k) {
-            a[k] = p[k];
-            b[k] = p[T + k];
-        }
-        unit_mul<T>(a, b, c);
-#pragma unroll
-        for (int k = 0; k < 2 * T; ++k) p[k] = c[k];
-    }
+// XOR a value into an LDS word: ds_xor_b32.  The order of the XORs into
+// one word does not change the result, so results are deterministic.
+__device__ __forceinline__ void lds_xor(u32 *p, u32 v) {
+    __hip_atomic_fetch_xor(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+
+// ------------------------------------------------------- operand sources
+// The first split of a Karatsuba subtree reads its root operands through a
+// source: word w of operand x (0 = a, 1 = b).
+struct LdsSource {
+    const u32 *ab;  // [a (S) | b (S)]
+    int S;
+    __device__ __forceinline__ u32 get(int x, int w) const { return ab[x * S + w]; }
+};
 
 // ----------------------------------------------------- 2-way Karatsuba levels
 // Splitting (KaratRec, Appendix A): a node of SL words with operands [a | b]
@@ -155,6 +152,21 @@ __device__ __forceinline__ void k2_split(const u32 *src, u32 *dst) {
     }
 }
 
+// The root split, reading the root operands from a source.
+template <int SL, class Src>
+__device__ __forceinline__ void k2_split_src(const Src &src, u32 *dst) {
+    constexpr int H = SL / 2;
+    for (int idx = threadIdx.x; idx < 2 * H; idx += NT) {
+        const int x = idx / H;
+        const int w = idx - x * H;
+        const u32 lo = src.get(x, w);
+        const u32 hi = src.get(x, H + w);
+        dst[idx] = lo;
+        dst[2 * H + idx] = hi;
+        dst[4 * H + idx] = lo ^ hi;
+    }
+}
+
 // Reconstruction (KaratRec): R = R0 + (R0 + R1 + R2) X^{32H} + R1 X^{64H}
 // with children products R_k of 2H words stored densely; since R0 and R1 are
 // adjacent, [R0 | R1] already is R0 + R1 X^{64H}.  Parent products are 4H
@@ -175,19 +187,29 @@ __device__ __forceinline__ void k2_merge(const u32 *src, u32 *dst) {
     }
 }
 
-// D levels of 2-way Karatsuba over T-word units, breadth first.
+// D levels of 2-way Karatsuba over T-word units, breadth first, 3^D <= NT
+// units (one per thread, one round).
 //   S       = T * 2^D operand words; the product has 2S words.
-//   scratch = [P (units: 2T * 3^D words) | DA (4T * 3^(D-1) words)].
-// Down pass: level D-1 lands in DA, level D-2 in P, alternating backwards,
-// and the units in P.  Up pass: alternates P -> DA -> P ...  Every buffer
-// a level is written to is dead at that point (see the alternation).
+//   scratch = [DA (level D-1: 3^(D-1) nodes x 4T words) | DB (3^(D-2) x 8T)].
+// Down pass: the root split reads the source; level L is stored in DA when
+// D-1-L is even, else in DB (so level D-1 lands in DA).  The units read
+// their operands from level D-1, i.e. they perform the last split while
+// loading.  The last merge is fused too: after every unit has loaded its
+// operands, level D-1 is cleared and each unit XORs its product into its
+// parent's product in place (LDS atomics), at offset T*k for child k:
+//   child 0 and 1 add [c_lo, c_lo + c_hi, c_hi], child 2 adds [c_lo, c_hi]
+// (the KaratRec reconstruction, distributed over the three children).  The
+// up pass then alternates DA -> DB -> DA ... with the same parity rule, and
+// every buffer written is dead at that point.
 template <int D, int T>
 struct ParK2 {
+    static_assert(D >= 0 && pow3(D) <= NT, "one unit per thread");
+    static constexpr bool IS_SEQ = false;
     static constexpr int S = T << D;
     static constexpr long long UNITS = pow3(D);
-    static constexpr int P_WORDS = (int)(2 * T * UNITS);
-    static constexpr int DA_WORDS = D > 0 ? (int)(4 * T * pow3(D - 1)) : 0;
-    static constexpr int SCRATCH = P_WORDS + DA_WORDS;
+    static constexpr int DA_WORDS = D >= 1 ? (int)(4 * T * pow3(D - 1)) : 2 * T;
+    static constexpr int DB_WORDS = D >= 2 ? (int)(8 * T * pow3(D - 2)) : 0;
+    static constexpr int SCRATCH = DA_WORDS + DB_WORDS;
     static constexpr long long BASE = UNITS * T * T;   // 32x32 word products
     // XOR lane-ops of one level of size SL over NL nodes: split SL, merge 3*SL.
     static constexpr long long xor_ops(int l) {
@@ -196,48 +218,108 @@ struct ParK2 {
     static constexpr long long OPS = UNITS * Unit<T>::OPS + xor_ops(0);
 
     template <int L>
-    __device__ static u32 *down_dst(u32 *P, u32 *DA) {
-        // destination of level L (1 <= L <= D)
-        if constexpr (L == D) return P;
-        else return ((D - 1 - L) % 2 == 0) ? DA : P;
+    __device__ __forceinline__ static u32 *level_buf(u32 *DA, u32 *DB) {
+        if constexpr (((D - 1 - L) % 2) == 0) return DA;
+        else return DB;
     }
 
+    // levels L -> L+1 for 1 <= L < D-1
     template <int L>
-    __device__ static void down(const u32 *src, u32 *P, u32 *DA) {
-        constexpr int SL = T << (D - L);
-        u32 *dst = down_dst<L + 1>(P, DA);
-        k2_split<(int)pow3(L), SL>(src, dst);
-        __syncthreads();
-        if constexpr (L + 1 < D) down<L + 1>(dst, P, DA);
-    }
-
-    template <int L>
-    __device__ static u32 *up(const u32 *src, u32 *P, u32 *DA) {
-        constexpr int H = T << (D - L - 1);
-        u32 *dst = ((D - L) % 2) ? DA : P;
-        k2_merge<(int)pow3(L), H>(src, dst);
-        __syncthreads();
-        if constexpr (L > 0) return up<L - 1>(dst, P, DA);
-        else return dst;
-    }
-
-    // in: [a (S) | b (S)]; returns the 2S-word product (inside scratch).
-    __device__ static u32 *run(const u32 *in, u32 *scratch) {
-        u32 *P = scratch;
-        u32 *DA = scratch + P_WORDS;
-        if constexpr (D == 0) {
-            for (int k = threadIdx.x; k < 2 * T; k += NT) P[k] = in[k];
+    __device__ __forceinline__ static void down(u32 *DA, u32 *DB) {
+        if constexpr (L + 1 <= D - 1) {
+            k2_split<(int)pow3(L), (T << (D - L))>(level_buf<L>(DA, DB), level_buf<L + 1>(DA, DB));
             __syncthreads();
-            run_units<T, 1>(P);
-            __syncthreads();
-            return P;
-        } else {
-            down<0>(in, P, DA);
-            run_units<T, (int)UNITS>(P);
-            __syncthreads();
-            return up<D - 1>(P, P, DA);
+            down<L + 1>(DA, DB);
         }
     }
+
+    // merges from level L+1 (products) to level L, down to the root
+    template <int L>
+    __device__ __forceinline__ static u32 *up(u32 *DA, u32 *DB) {
+        if constexpr (L < 0) {
+            return level_buf<0>(DA, DB);
+        } else {
+            k2_merge<(int)pow3(L), (T << (D - L - 1))>(level_buf<L + 1>(DA, DB), level_buf<L>(DA, DB));
+            __syncthreads();
+            return up<L - 1>(DA, DB);
+        }
+    }
+
+    // The unit phase: load (last split), clear level D-1, multiply, XOR the
+    // product into the parent (last merge).  Source Src is only used for D == 1.
+    template <class Src>
+    __device__ __forceinline__ static void units(const Src &src, u32 *DA) {
+        const int u = threadIdx.x;
+        const bool active = u < (int)UNITS;
+        const int v = u / 3, k = u - 3 * (u / 3);
+        u32 a[T], b[T], c[2 * T];
+        if (active) {
+#pragma unroll
+            for (int w = 0; w < T; ++w) {
+                u32 alo, ahi, blo, bhi;
+                if constexpr (D == 1) {
+                    alo = src.get(0, w);
+                    ahi = src.get(0, T + w);
+                    blo = src.get(1, w);
+                    bhi = src.get(1, T + w);
+                } else {
+                    const u32 *node = DA + v * 4 * T;  // [a_v (2T) | b_v (2T)]
+                    alo = node[w];
+                    ahi = node[T + w];
+                    blo = node[2 * T + w];
+                    bhi = node[3 * T + w];
+                }
+                a[w] = (k != 1 ? alo : 0u) ^ (k != 0 ? ahi : 0u);
+                b[w] = (k != 1 ? blo : 0u) ^ (k != 0 ? bhi : 0u);
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < DA_WORDS; i += NT) DA[i] = 0;
+        __syncthreads();
+        if (active) {
+            unit_mul<T>(a, b, c);
+            u32 *q = DA + v * 4 * T + T * (k < 2 ? k : 1);
+#pragma unroll
+            for (int w = 0; w < T; ++w) {
+                lds_xor(q + w, c[w]);
+                lds_xor(q + T + w, k < 2 ? (c[w] ^ c[T + w]) : c[T + w]);
+                if (k < 2) lds_xor(q + 2 * T + w, c[T + w]);
+            }
+        }
+        __syncthreads();
+    }
+
+    // Product of the root operands given by src; returns its 2S words.
+    template <class Src>
+    __device__ __forceinline__ static u32 *run_src(const Src &src, u32 *scratch) {
+        u32 *DA = scratch;
+        u32 *DB = scratch + DA_WORDS;
+        if constexpr (D == 0) {
+            u32 a[T], b[T], c[2 * T];
+            if (threadIdx.x == 0) {
+#pragma unroll
+                for (int w = 0; w < T; ++w) {
+                    a[w] = src.get(0, w);
+                    b[w] = src.get(1, w);
+                }
+                unit_mul<T>(a, b, c);
+#pragma unroll
+                for (int w = 0; w < 2 * T; ++w) DA[w] = c[w];
+            }
+            __syncthreads();
+            return DA;
+        } else {
+            if constexpr (D >= 2) {
+                k2_split_src<S>(src, level_buf<1>(DA, DB));
+                __syncthreads();
+                down<1>(DA, DB);
+            }
+            units(src, DA);
+            return up<D - 2>(DA, DB);
+        }
+    }
+
+    __device__ __forceinline__ static u32 *run_ab(const u32 *ab, u32 *scratch) { return run_src(LdsSource{ab, S}, scratch); }
 };
 
 // --------------------------------------------------------- workgroup scans
@@ -310,73 +392,93 @@ __device__ __forceinline__ void div_xx1_pair(u32 *x, u32 *y, u32 *tmp) {
 //   R = c0 (1 + Y) + C(1) Y + c2 (Y + Y^2) + c3 (Y + Y^3) + c4 (Y + Y^4).
 // Each point product is folded into R and into the two numerators as soon as
 // it is computed, so only one child product is alive at a time.
+// Operands of Toom-3 point E (0: 0, 1: 1, 2: x, 3: x+1, 4: inf) computed
+// on the fly from the parent's [a | b] (S = 3m words each):
+//   e0 = a0, e1 = a0+a1+a2, ex = a0 + x a1 + x^2 a2, ex1 = e1 + x a1 + x^2 a2,
+//   einf = a2, with x a word shift.
+template <int E>
+struct EvalSource {
+    const u32 *ab;
+    int S, m;
+    __device__ __forceinline__ u32 part(int x, int p, int j) const {
+        return (j >= 0 && j < m) ? ab[x * S + p * m + j] : 0u;
+    }
+    __device__ __forceinline__ u32 get(int x, int w) const {
+        if constexpr (E == 0) return part(x, 0, w);
+        else if constexpr (E == 1) return part(x, 0, w) ^ part(x, 1, w) ^ part(x, 2, w);
+        else if constexpr (E == 2) return part(x, 0, w) ^ part(x, 1, w - 1) ^ part(x, 2, w - 2);
+        else if constexpr (E == 3)
+            return part(x, 0, w) ^ part(x, 1, w) ^ part(x, 2, w) ^ part(x, 1, w - 1) ^ part(x, 2, w - 2);
+        else return part(x, 2, w);
+    }
+};
+
 template <class Child>
 struct SeqT3 {
+    static constexpr bool IS_SEQ = true;
     static constexpr int S1 = Child::S;
     static constexpr int m = S1 - 2;
     static constexpr int S = 3 * m;
     static constexpr int R_WORDS = 6 * m;
     static constexpr int SA_WORDS = 2 * S1 + 2;
     static constexpr int UA_WORDS = 2 * S1 + 2;
-    static constexpr int CIN_WORDS = 2 * S1;
+    // a Toom-3 child needs its operands materialised (it reads them five
+    // times); a Karatsuba child reads them through its root split
+    static constexpr int CIN_WORDS = Child::IS_SEQ ? 2 * S1 : 0;
     static constexpr int TMP_WORDS = 2 * NWAVE;
     static constexpr int SCRATCH = R_WORDS + SA_WORDS + UA_WORDS + CIN_WORDS + TMP_WORDS + Child::SCRATCH;
     static constexpr long long BASE = 5 * Child::BASE;
     // evaluation 16*S1, absorption 30*S1, divisions 4m, recombination 8m
     static constexpr long long OPS = 5 * Child::OPS + 46LL * S1 + 12LL * m;
 
-    // Operands of point e (0: 0, 1: 1, 2: x, 3: x+1, 4: inf) into cin.
-    template <int E>
-    __device__ static void eval(const u32 *A, u32 *cin) {
-        par_map<2 * S1>(cin, [&](int idx) -> u32 {
-            const int x = idx / S1;
-            const int w = idx - x * S1;
-            const u32 *p = A + x * S;  // [a | b] layout, each S words
-            auto get = [&](int part, int j) -> u32 {
-                return (j >= 0 && j < m) ? p[part * m + j] : 0u;
-            };
-            if constexpr (E == 0) return get(0, w);
-            else if constexpr (E == 1) return get(0, w) ^ get(1, w) ^ get(2, w);
-            else if constexpr (E == 2) return get(0, w) ^ get(1, w - 1) ^ get(2, w - 2);
-            else if constexpr (E == 3)
-                return get(0, w) ^ get(1, w) ^ get(2, w) ^ get(1, w - 1) ^ get(2, w - 2);
-            else return get(2, w);
-        });
-    }
-
     // Fold point product p (2*S1 words) into R and the numerators Sa, Ua.
     template <int E>
-    __device__ static void absorb(const u32 *p, u32 *R, u32 *Sa, u32 *Ua) {
+    __device__ __forceinline__ static void absorb(const u32 *p, u32 *R, u32 *Sa, u32 *Ua) {
         auto P = [&](int j) -> u32 { return (j >= 0 && j < 2 * S1) ? p[j] : 0u; };
         if constexpr (E == 0 || E == 1 || E == 4) {
-            par_map<R_WORDS>(R, [&](int r) -> u32 {
-                if constexpr (E == 0) return R[r] ^ P(r) ^ P(r - m);
-                else if constexpr (E == 1) return R[r] ^ P(r - m);
-                else return R[r] ^ P(r - m) ^ P(r - 4 * m);
-            });
+            for (int r = threadIdx.x; r < R_WORDS; r += NT) {
+                u32 v;
+                if constexpr (E == 0) v = P(r) ^ P(r - m);
+                else if constexpr (E == 1) v = P(r - m);
+                else v = P(r - m) ^ P(r - 4 * m);
+                R[r] ^= v;
+            }
         }
-        if constexpr (E != 4) par_map<2 * S1>(Sa, [&](int k) -> u32 { return Sa[k] ^ p[k]; });
+        if constexpr (E != 4) {
+            for (int k = threadIdx.x; k < 2 * S1; k += NT) Sa[k] ^= p[k];
+        }
         if constexpr (E != 0) {
-            par_map<UA_WORDS>(Ua, [&](int k) -> u32 {
-                if constexpr (E == 1) return Ua[k] ^ P(k);
-                else if constexpr (E == 2) return Ua[k] ^ P(k - 1);
-                else if constexpr (E == 3) return Ua[k] ^ P(k) ^ P(k - 1);
-                else return Ua[k] ^ P(k - 1) ^ P(k - 4);
-            });
+            for (int k = threadIdx.x; k < UA_WORDS; k += NT) {
+                u32 v;
+                if constexpr (E == 1) v = P(k);
+                else if constexpr (E == 2) v = P(k - 1);
+                else if constexpr (E == 3) v = P(k) ^ P(k - 1);
+                else v = P(k - 1) ^ P(k - 4);
+                Ua[k] ^= v;
+            }
         }
     }
 
     template <int E>
-    __device__ static void point(const u32 *in, u32 *R, u32 *Sa, u32 *Ua, u32 *cin, u32 *cs) {
-        eval<E>(in, cin);
-        __syncthreads();
-        const u32 *p = Child::run(cin, cs);
+    __device__ __forceinline__ static void point(const u32 *ab, u32 *R, u32 *Sa, u32 *Ua, u32 *cin, u32 *cs) {
+        const EvalSource<E> src{ab, S, m};
+        const u32 *p;
+        if constexpr (Child::IS_SEQ) {
+            par_map<2 * S1>(cin, [&](int idx) -> u32 {
+                const int x = idx / S1;
+                return src.get(x, idx - x * S1);
+            });
+            __syncthreads();
+            p = Child::run_ab(cin, cs);
+        } else {
+            p = Child::run_src(src, cs);
+        }
         absorb<E>(p, R, Sa, Ua);
         __syncthreads();
     }
 
-    // in: [a (S) | b (S)]; returns the 2S-word product (inside scratch).
-    __device__ static u32 *run(const u32 *in, u32 *scratch) {
+    // ab: [a (S) | b (S)] in LDS; returns the 2S-word product (inside scratch).
+    __device__ __forceinline__ static u32 *run_ab(const u32 *ab, u32 *scratch) {
         u32 *R = scratch;
         u32 *Sa = R + R_WORDS;
         u32 *Ua = Sa + SA_WORDS;
@@ -384,12 +486,12 @@ struct SeqT3 {
         u32 *tmp = cin + CIN_WORDS;
         u32 *cs = tmp + TMP_WORDS;
         for (int k = threadIdx.x; k < R_WORDS + SA_WORDS + UA_WORDS; k += NT) R[k] = 0;
-        // (the barrier inside point<0> orders these stores before any absorb)
-        point<0>(in, R, Sa, Ua, cin, cs);
-        point<1>(in, R, Sa, Ua, cin, cs);
-        point<2>(in, R, Sa, Ua, cin, cs);
-        point<3>(in, R, Sa, Ua, cin, cs);
-        point<4>(in, R, Sa, Ua, cin, cs);
+        // (the barriers inside the first child run order these stores before any absorb)
+        point<0>(ab, R, Sa, Ua, cin, cs);
+        point<1>(ab, R, Sa, Ua, cin, cs);
+        point<2>(ab, R, Sa, Ua, cin, cs);
+        point<3>(ab, R, Sa, Ua, cin, cs);
+        point<4>(ab, R, Sa, Ua, cin, cs);
         div_xx1_pair<2 * m>(Sa, Ua, tmp);  // Sa <- c3, Ua <- c2 (first 2m words)
         auto c3 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Sa[j] : 0u; };
         auto c2 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Ua[j] : 0u; };

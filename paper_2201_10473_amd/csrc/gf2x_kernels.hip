@@ -8,7 +8,7 @@
 namespace gf2x {
 
 template <class Sch>
-__global__ __launch_bounds__(NT) void k_single(const uint64_t *a, const uint64_t *b, uint64_t *c, u32 n,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_per_simd<Sch>()))) void k_single(const uint64_t *a, const uint64_t *b, uint64_t *c, u32 n,
                                                u32 kind) {
     extern __shared__ u32 smem[];
     one_product<Sch>(a, b, c, n, kind, smem);
@@ -16,7 +16,7 @@ __global__ __launch_bounds__(NT) void k_single(const uint64_t *a, const uint64_t
 
 // Persistent workgroups over a batch whose items all use class Sch.
 template <class Sch>
-__global__ __launch_bounds__(NT) void k_batched(const DevItem *items, u32 count, uint64_t *c_base,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_per_simd<Sch>()))) void k_batched(const DevItem *items, u32 count, uint64_t *c_base,
                                                 const uint64_t *a_base, const uint64_t *b_base) {
     extern __shared__ u32 smem[];
     for (u32 i = blockIdx.x; i < count; i += gridDim.x) {

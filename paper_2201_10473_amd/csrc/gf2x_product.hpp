@@ -76,6 +76,15 @@ static_assert(NUM_CLASSES == kNumClasses, "class count mismatch");
 template <class Sch>
 constexpr int lds_words() { return 2 * Sch::S + Sch::SCRATCH; }
 
+// Workgroups of a class that fit in one CU's 160 KB of LDS; with 4 waves per
+// workgroup this is also the number of waves per SIMD the register
+// allocation should leave room for (at most 8).
+template <class Sch>
+constexpr int waves_per_simd() {
+    const int wg = (160 * 1024) / (lds_words<Sch>() * 4);
+    return wg < 1 ? 1 : (wg > 8 ? 8 : wg);
+}
+
 #define GF2X_CHECK_LDS(id, name, T) \
     static_assert(lds_words<T>() * 4 <= 160 * 1024, "class " name " exceeds LDS");
 GF2X_CLASS_LIST(GF2X_CHECK_LDS)
@@ -137,7 +146,7 @@ __device__ __forceinline__ void one_product(const uint64_t *a, const uint64_t *b
     constexpr int S = Sch::S;
     stage<S>(a, b, n, smem);
     __syncthreads();
-    const u32 *R = Sch::run(smem, smem + 2 * S);
+    const u32 *R = Sch::run_ab(smem, smem + 2 * S);
     if (kind == kKindCyclic) store_cyclic<S>(R, n, c);
     else store_full<S>(R, n, c);
     __syncthreads();  // LDS is reused by the next product of a persistent loop

@@ -52,6 +52,11 @@ static inline int emu_sbfe(int a, int offset, int width) {
 static inline uint32_t emu_alignbit(uint32_t hi, uint32_t lo, uint32_t s) {
     return (uint32_t)(((((uint64_t)hi) << 32) | lo) >> (s & 31u));
 }
+#ifndef __HIP_MEMORY_SCOPE_WORKGROUP
+#define __HIP_MEMORY_SCOPE_WORKGROUP 3
+#endif
+static inline uint32_t emu_atomic_xor(uint32_t *p, uint32_t v) { return __atomic_fetch_xor(p, v, __ATOMIC_RELAXED); }
+#define __hip_atomic_fetch_xor(p, v, order, scope) emu_atomic_xor((p), (v))
 #define __builtin_amdgcn_bitop3_b32(a, b, c, imm) emu_bitop3((a), (b), (c), (imm))
 #define __builtin_amdgcn_sbfe(a, o, w) emu_sbfe((a), (o), (w))
 #define __builtin_amdgcn_alignbit(h, l, s) emu_alignbit((h), (l), (s))
