@@ -221,6 +221,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-one-per-launch", action="store_true")
     ap.add_argument("--only-n", type=int, default=0, help="time only this ring size (profiling runs)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU; multi-GPU runs are not part of this library's benchmark "
@@ -236,6 +238,13 @@ def main():
         sys.exit(1)
     ctx = gf2x.Context(0)
     seed = inputs.SEED_BASE + 2
+    if args.calibrate_copy_mib:
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: %d bytes read, %d bytes written" % (nbytes, nbytes))
     sizes = [args.only_n] if args.only_n else [17669, 57637]
     results = {}
     for n in sizes:
