@@ -134,6 +134,48 @@ def time_shared(ctx, n, count, flags, steps, seed):
     return ms, h, R, C
 
 
+def time_mixed(ctx, steps, seed, count=8192):
+    """The mixed workload: n uniform over the six ring sizes, odd items dense x
+    sparse (weight by size level), all in one graph-captured launch sequence."""
+    import numpy as np
+    import torch
+
+    from paper_2201_10473_amd import gf2x, inputs, serve
+
+    ns, off, A, B = serve.make_requests(count, seed)
+    for i in range(1, count, 2):
+        n = int(ns[i])
+        W = (n + 63) // 64
+        B[int(off[i]):int(off[i]) + W] = inputs.sparse(n, inputs.sparse_weight_for(n), seed, i)
+    items = gf2x.make_items(ns, gf2x.KIND_CYCLIC, off, off, off)
+    dA = torch.from_numpy(A.view(np.int64)).cuda()
+    dB = torch.from_numpy(B.view(np.int64)).cuda()
+    dC = torch.zeros(len(A), dtype=torch.int64, device="cuda")
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.3:
+        ctx.mul_batched(items, dC, dA, dB, gf2x.USE_GRAPH)
+        torch.cuda.synchronize()
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s_ev.record()
+    for _ in range(steps):
+        ctx.mul_batched(items, dC, dA, dB, gf2x.USE_GRAPH)
+    e_ev.record()
+    torch.cuda.synchronize()
+    ms = s_ev.elapsed_time(e_ev) / steps
+    C = dC.cpu().numpy().view(np.uint64)
+    import oracle
+
+    for i in (0, 1, count - 1):
+        n = int(ns[i])
+        W = (n + 63) // 64
+        sl = slice(int(off[i]), int(off[i]) + W)
+        if not np.array_equal(C[sl], oracle.mul_cyclic(A[sl], B[sl], n)):
+            raise AssertionError("mixed workload item %d differs from the oracle" % i)
+    ops = sum(ctx.schedule_info(int(n))[2] for n in ns)
+    return {"products": count, "ms_per_launch": round(ms, 4), "products_per_s": round(count / (ms * 1e-3), 1),
+            "valu_frac": round(ops / (ms * 1e-3) / VALU_PEAK, 4)}
+
+
 def check_sample(res, n, count, k=6):
     """Spot-check k items against the oracle and all items against parity."""
     import numpy as np
@@ -221,6 +263,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-one-per-launch", action="store_true")
     ap.add_argument("--only-n", type=int, default=0, help="time only this ring size (profiling runs)")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=20000)
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -295,6 +339,22 @@ def main():
             }
             log("  packed %.3f ms, toeplitz %.3f ms" % (ms_p, ms_t))
 
+    mixed = None
+    serving = []
+    if not args.only_n:
+        log("mixed workload: 8192 products, six sizes, half dense x sparse")
+        mixed = time_mixed(ctx, 10, inputs.SEED_BASE + 4)
+        log("  %s" % mixed)
+        if not args.no_serving:
+            from paper_2201_10473_amd import serve
+
+            for rate in (10000, 100000, 500000):
+                log("serving: Poisson %d req/s" % rate)
+                res, bufs = serve.run(ctx, rate, args.serving_requests, inputs.SEED_BASE + 5)
+                serve.check_against_batched(ctx, *bufs)
+                serving.append(res)
+                log("  achieved %.0f req/s p50 %.1f us p99 %.1f us" % (res["achieved_rate"], res["p50_us"], res["p99_us"]))
+
     head = sizes[0]
     main_res = results[head]
     achieved = main_res["lane_ops_per_product"] * BATCH / (main_res["launch_ms"] * 1e-3)
@@ -333,6 +393,8 @@ def main():
             {str(n): {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
              for n, r in results.items()},
             shared_operand=shared,
+            mixed=mixed,
+            serving=serving,
         ),
     }
     if not args.no_cpu_baseline:

@@ -55,6 +55,7 @@ typedef struct ihipStream_t *gf2x_stream_t;
 #define GF2X_EINVAL (-1)  /* bad argument: null pointer, n out of range, misaligned or overlapping buffers */
 #define GF2X_ENOMEM (-2)  /* a device workspace could not be allocated                                     */
 #define GF2X_EDEVICE (-3) /* a HIP runtime call failed; gf2x_last_device_error() names it                   */
+#define GF2X_EAGAIN (-4)  /* serving: the host queue is full, submit again later (backpressure)            */
 #define GF2X_ENOTSUP (-5) /* the request is valid but this build cannot serve it (see gf2x_mul_batched)    */
 
 /* Largest supported n, in bits (the paper's largest operand size, Table perfKaratRec). */
@@ -147,6 +148,70 @@ int gf2x_schedule_info(gf2x_ctx *ctx, uint32_t n_bits, uint32_t *padded_words32,
  * reads).  This call is synchronous: it waits for the device on a private
  * stream.  Errors: GF2X_EINVAL, GF2X_ENOMEM, GF2X_EDEVICE. */
 int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t batch, const char *out_path);
+
+/* ------------------------------------------------------------------ serving
+ * Continuous batching of ring products (Section 1's products, arriving as a
+ * stream of requests) on one context.  A scheduler thread keeps `streams`
+ * slots; each slot holds up to max_batch requests of at most max_bits bits in
+ * its own device and pinned host buffers, and the device buffers together
+ * stay within hbm_budget_bytes.  Requests whose arrival time has passed are
+ * admitted into free slots in submission order; while a slot's batch runs,
+ * later arrivals form the next batch on another slot, so their work overlaps
+ * on the device.  Results are identical to gf2x_mul_cyclic of the same
+ * operands (the same kernels run them). */
+typedef struct gf2x_srv gf2x_srv;
+
+typedef struct gf2x_srv_opts {
+    size_t hbm_budget_bytes; /* device memory for in-flight requests (0 = 256 MiB)          */
+    uint32_t streams;        /* concurrent batches, 1..16 (0 = 4)                           */
+    uint32_t max_bits;       /* largest n that will be submitted (0 = 57637)                */
+    uint32_t max_batch;      /* cap on requests per batch (0 = as many as the budget allows) */
+    uint32_t max_pending;    /* host queue length before GF2X_EAGAIN (0 = 4M)               */
+    uint32_t flags;          /* reserved, must be 0                                         */
+} gf2x_srv_opts;
+
+typedef struct gf2x_srv_stats {
+    uint64_t submitted, admitted, completed, refused, pending;
+    uint64_t batches, launches;
+    uint32_t max_batch, max_batch_seen, max_slots_busy;
+    uint64_t hbm_bytes; /* device memory held by the slots */
+} gf2x_srv_stats;
+
+/* Start a server on ctx (which must outlive it).  Errors: GF2X_EINVAL,
+ * GF2X_ENOMEM (budget below one request per stream, or allocation failed),
+ * GF2X_EDEVICE. */
+int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts);
+
+/* Submit `count` requests.  Request i multiplies the HOST polynomials at
+ * a_base + a_off[i] and b_base + b_off[i] (W(n_bits[i]) words each, read when
+ * the request is admitted) and writes the ring product to the HOST words at
+ * c_base + c_off[i] when it completes; the caller keeps all three alive until
+ * then.  arrival_ns[i] (steady clock, gf2x_srv_now_ns; NULL = now) is the
+ * earliest admission time.  Tickets first_ticket .. first_ticket+count-1 are
+ * assigned in order.  Errors: GF2X_EINVAL (n above max_bits, null pointers),
+ * GF2X_EAGAIN (host queue full: nothing was queued), a pending device error. */
+int gf2x_srv_submit(gf2x_srv *srv, uint32_t count, const uint32_t *n_bits, const uint64_t *a_base,
+                    const uint64_t *a_off, const uint64_t *b_base, const uint64_t *b_off, uint64_t *c_base,
+                    const uint64_t *c_off, const uint64_t *arrival_ns, uint64_t *first_ticket);
+
+/* Completion stamps (steady clock ns; 0 = not yet complete) of tickets
+ * first_ticket .. first_ticket+count-1.  Errors: GF2X_EINVAL, or the device
+ * error the scheduler hit. */
+int gf2x_srv_completion(gf2x_srv *srv, uint64_t first_ticket, uint32_t count, uint64_t *done_ns);
+
+/* Wait until every submitted request has completed (timeout_ms 0 = 1 hour).
+ * Returns GF2X_EAGAIN on timeout. */
+int gf2x_srv_drain(gf2x_srv *srv, uint64_t timeout_ms);
+
+/* Counters of the server.  Errors: GF2X_EINVAL. */
+int gf2x_srv_get_stats(gf2x_srv *srv, gf2x_srv_stats *stats);
+
+/* Steady-clock time in ns, the time base of arrival and completion stamps. */
+uint64_t gf2x_srv_now_ns(void);
+
+/* Stop the server after the queued requests complete, and free it.  NULL is
+ * accepted. */
+void gf2x_srv_destroy(gf2x_srv *srv);
 
 /* Static message for a GF2X_E* code. */
 const char *gf2x_strerror(int code);

@@ -21,7 +21,7 @@ ARCH = "gfx950"
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 
-SOURCES = ["gf2x_kernels.hip", "gf2x_toeplitz.hip", "gf2x_api.cpp"]
+SOURCES = ["gf2x_kernels.hip", "gf2x_toeplitz.hip", "gf2x_api.cpp", "gf2x_serve.cpp"]
 
 
 def _compile(src):

@@ -14,6 +14,7 @@
 
 #include "gf2x.h"
 #include "gf2x_internal.hpp"
+#include "gf2x_ctx.hpp"
 #include "gf2x_toeplitz.hpp"
 
 using namespace gf2x;
@@ -37,32 +38,8 @@ int device_error(hipError_t e) {
 
 uint64_t words64(uint32_t n) { return ((uint64_t)n + 63u) / 64u; }
 
-struct GraphEntry {
-    hipGraphExec_t exec = nullptr;
-    hipGraph_t graph = nullptr;
-    DevItem *items = nullptr;  // private copy of the descriptors
-    uint64_t checksum = 0;
-};
-
 }  // namespace
 
-struct gf2x_ctx {
-    int device = 0;
-    int num_cu = 0;
-    size_t budget = 0;
-    size_t allocated = 0;
-    int cls_of_w32[kMaxWords32 + 1];
-    uint8_t *d_cls = nullptr;      // device copy of cls_of_w32
-    DevItem *d_items = nullptr;    // workspace for host item descriptors
-    size_t d_items_cap = 0;
-    hipEvent_t ws_free = nullptr;  // recorded after the last launch reading d_items
-    bool ws_used = false;
-    std::map<std::tuple<const void *, uint32_t, const void *, const void *, const void *, uint32_t, void *>,
-             GraphEntry>
-        graphs;
-    toeplitz::Workspace tz;
-    std::map<uint32_t, int> tuned;  // w32 -> class chosen by gf2x_tune or the cache file
-};
 
 namespace {
 
@@ -148,34 +125,66 @@ uint64_t checksum(const gf2x_item *items, uint32_t count) {
     return h;
 }
 
-// Host descriptors -> validated DevItems ordered by decreasing n (stable).
-int build_items(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, std::vector<DevItem> &out, bool &uniform,
-                int &cls0, int &max_lds) {
+// Host descriptors -> validated DevItems grouped by class, classes ordered
+// by decreasing size, items in each group in submission order.  groups:
+// (class, first index, count).
+struct Group {
+    int cls;
+    uint32_t first, count;
+};
+
+int build_items(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, std::vector<DevItem> &out,
+                std::vector<Group> &groups) {
     out.resize(count);
-    uniform = true;
-    cls0 = -1;
-    max_lds = 0;
     for (uint32_t i = 0; i < count; ++i) {
         const gf2x_item &it = items[i];
         if (it.n_bits == 0 || it.n_bits > kMaxBits) return GF2X_EINVAL;
         if (it.kind != GF2X_KIND_CYCLIC && it.kind != GF2X_KIND_FULL) return GF2X_EINVAL;
         const int cls = ctx->cls_of_w32[(it.n_bits + 31u) / 32u];
         out[i] = DevItem{it.n_bits, it.kind, (uint32_t)cls, 0u, it.a_off, it.b_off, it.c_off};
-        if (cls0 < 0) cls0 = cls;
-        if (cls != cls0) uniform = false;
-        max_lds = std::max(max_lds, class_info(cls).lds_bytes);
     }
-    if (!uniform)
-        std::stable_sort(out.begin(), out.end(), [](const DevItem &x, const DevItem &y) { return x.n > y.n; });
+    std::stable_sort(out.begin(), out.end(), [](const DevItem &x, const DevItem &y) {
+        const int sx = class_info((int)x.cls).S, sy = class_info((int)y.cls).S;
+        return sx != sy ? sx > sy : x.cls < y.cls;
+    });
+    groups.clear();
+    for (uint32_t i = 0; i < count; ++i) {
+        if (groups.empty() || groups.back().cls != (int)out[i].cls) groups.push_back(Group{(int)out[i].cls, i, 0});
+        groups.back().count++;
+    }
     return GF2X_OK;
 }
 
-int launch_items(gf2x_ctx *ctx, const DevItem *d_items, uint32_t count, bool uniform, int cls0, int max_lds,
-                 uint64_t *c, const uint64_t *a, const uint64_t *b, hipStream_t s) {
-    hipError_t e;
-    if (uniform) e = launch_batched(cls0, d_items, count, c, a, b, ctx->num_cu, s);
-    else e = launch_mixed(d_items, count, c, a, b, ctx->d_cls, false, max_lds, ctx->num_cu, s);
-    if (e != hipSuccess) return device_error(e);
+int ensure_forks(gf2x_ctx *ctx) {
+    if (ctx->fork_stream[0]) return GF2X_OK;
+    for (int i = 0; i < gf2x_ctx::kForks; ++i) HIP_TRY(hipStreamCreateWithFlags(&ctx->fork_stream[i], hipStreamNonBlocking));
+    for (int i = 0; i <= gf2x_ctx::kForks; ++i) HIP_TRY(hipEventCreateWithFlags(&ctx->fork_event[i], hipEventDisableTiming));
+    return GF2X_OK;
+}
+
+// One launch per class group.  A single group goes straight onto s; several
+// groups are spread over the context's internal streams, forked from s and
+// joined back to it with events, so that different sizes overlap.
+int launch_groups(gf2x_ctx *ctx, const DevItem *d_items, const std::vector<Group> &groups, uint64_t *c,
+                  const uint64_t *a, const uint64_t *b, hipStream_t s) {
+    if (groups.size() == 1) {
+        const Group &g = groups[0];
+        hipError_t e = launch_batched(g.cls, d_items + g.first, g.count, c, a, b, ctx->num_cu, s);
+        return e == hipSuccess ? GF2X_OK : device_error(e);
+    }
+    int rc = ensure_forks(ctx);
+    if (rc) return rc;
+    const int K = std::min<int>(gf2x_ctx::kForks, (int)groups.size());
+    HIP_TRY(hipEventRecord(ctx->fork_event[gf2x_ctx::kForks], s));
+    for (int k = 0; k < K; ++k) HIP_TRY(hipStreamWaitEvent(ctx->fork_stream[k], ctx->fork_event[gf2x_ctx::kForks], 0));
+    for (size_t i = 0; i < groups.size(); ++i) {
+        const Group &g = groups[i];
+        HIP_TRY(launch_batched(g.cls, d_items + g.first, g.count, c, a, b, ctx->num_cu, ctx->fork_stream[i % K]));
+    }
+    for (int k = 0; k < K; ++k) {
+        HIP_TRY(hipEventRecord(ctx->fork_event[k], ctx->fork_stream[k]));
+        HIP_TRY(hipStreamWaitEvent(s, ctx->fork_event[k], 0));
+    }
     return GF2X_OK;
 }
 
@@ -191,6 +200,7 @@ const char *gf2x_strerror(int code) {
         case GF2X_EINVAL: return "invalid argument";
         case GF2X_ENOMEM: return "device workspace exceeds the budget or could not be allocated";
         case GF2X_EDEVICE: return "HIP runtime error";
+        case GF2X_EAGAIN: return "queue full or timed out; try again later";
         case GF2X_ENOTSUP: return "unsupported combination of flags";
         default: return "unknown error code";
     }
@@ -245,6 +255,10 @@ void gf2x_destroy(gf2x_ctx *ctx) {
         if (kv.second.items) hipFree(kv.second.items);
     }
     toeplitz::release(ctx->tz);
+    for (int i = 0; i < gf2x_ctx::kForks; ++i)
+        if (ctx->fork_stream[i]) hipStreamDestroy(ctx->fork_stream[i]);
+    for (int i = 0; i <= gf2x_ctx::kForks; ++i)
+        if (ctx->fork_event[i]) hipEventDestroy(ctx->fork_event[i]);
     if (ctx->d_items) hipFree(ctx->d_items);
     if (ctx->d_cls) hipFree(ctx->d_cls);
     if (ctx->ws_free) hipEventDestroy(ctx->ws_free);
@@ -315,9 +329,8 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
         }
     }
     std::vector<DevItem> host;
-    bool uniform = true;
-    int cls0 = -1, max_lds = 0;
-    int rc = build_items(ctx, items, count, host, uniform, cls0, max_lds);
+    std::vector<Group> groups;
+    int rc = build_items(ctx, items, count, host, groups);
     if (rc) return rc;
 
     if (flags & GF2X_USE_GRAPH) {
@@ -337,12 +350,12 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
             g.checksum = sum;
             if (hipMalloc(&g.items, count * sizeof(DevItem)) != hipSuccess) return GF2X_ENOMEM;
             HIP_TRY(hipMemcpyAsync(g.items, host.data(), count * sizeof(DevItem), hipMemcpyHostToDevice, s));
-            // capture the launch on a private stream, ordered after the copy
+            // capture the launches on a private stream, ordered after the copy
             hipStream_t cap;
             HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                int lrc = launch_items(ctx, g.items, count, uniform, cls0, max_lds, c_base, a_base, b_base, cap);
+                int lrc = launch_groups(ctx, g.items, groups, c_base, a_base, b_base, cap);
                 hipError_t e2 = hipStreamEndCapture(cap, &g.graph);
                 if (lrc) e = hipErrorLaunchFailure;
                 else e = e2;
@@ -364,7 +377,7 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
     if (rc) return rc;
     if (ctx->ws_used) HIP_TRY(hipStreamWaitEvent(s, ctx->ws_free, 0));
     HIP_TRY(hipMemcpyAsync(ctx->d_items, host.data(), count * sizeof(DevItem), hipMemcpyHostToDevice, s));
-    rc = launch_items(ctx, ctx->d_items, count, uniform, cls0, max_lds, c_base, a_base, b_base, s);
+    rc = launch_groups(ctx, ctx->d_items, groups, c_base, a_base, b_base, s);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(ctx->ws_free, s));
     ctx->ws_used = true;

@@ -1,0 +1,46 @@
+// gf2x_ctx.hpp -- the context object behind the opaque gf2x_ctx handle
+// (shared by the C ABI layer and the serving loop).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <tuple>
+
+#include "gf2x.h"
+#include "gf2x_internal.hpp"
+#include "gf2x_toeplitz.hpp"
+
+namespace gf2x {
+
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    DevItem *items = nullptr;  // private copy of the descriptors
+    uint64_t checksum = 0;
+};
+
+}  // namespace gf2x
+
+struct gf2x_ctx {
+    int device = 0;
+    int num_cu = 0;
+    size_t budget = 0;
+    size_t allocated = 0;
+    int cls_of_w32[gf2x::kMaxWords32 + 1];
+    uint8_t *d_cls = nullptr;      // device copy of cls_of_w32
+    gf2x::DevItem *d_items = nullptr;    // workspace for host item descriptors
+    size_t d_items_cap = 0;
+    hipEvent_t ws_free = nullptr;  // recorded after the last launch reading d_items
+    bool ws_used = false;
+    std::map<std::tuple<const void *, uint32_t, const void *, const void *, const void *, uint32_t, void *>,
+             gf2x::GraphEntry>
+        graphs;
+    gf2x::toeplitz::Workspace tz;
+    std::map<uint32_t, int> tuned;  // w32 -> class chosen by gf2x_tune or the cache file
+    // internal streams (default priority) for concurrent per-class launches,
+    // forked from and joined back to the caller's stream with events
+    static constexpr int kForks = 4;
+    hipStream_t fork_stream[kForks] = {};
+    hipEvent_t fork_event[kForks + 1] = {};
+};

@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+
 #include "gf2x_product.hpp"
 
 namespace gf2x {
@@ -103,10 +106,18 @@ hipError_t launch_single(int cls, const uint64_t *a, const uint64_t *b, uint64_t
     return hipGetLastError();
 }
 
+// Resident workgroups per CU of a kernel at a given dynamic LDS size (cached:
+// the runtime query is not free and the answer never changes).
 static int occupancy(const void *fn, int lds_bytes) {
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find({fn, lds_bytes});
+    if (it != cache.end()) return it->second;
     int blocks = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, fn, NT, lds_bytes) != hipSuccess || blocks < 1)
         blocks = 1;
+    cache[{fn, lds_bytes}] = blocks;
     return blocks;
 }
 

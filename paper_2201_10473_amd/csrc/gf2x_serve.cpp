@@ -1,0 +1,416 @@
+// gf2x_serve.cpp -- continuous batching of ring products with admission by
+// an HBM budget (the serving API of include/gf2x.h).
+//
+// Requests are ring products of any supported n with host operands.  A
+// scheduler thread owns K stream slots; each slot has a pinned host buffer
+// and a device buffer sized for `max_batch` requests of the largest n.  The
+// device buffers together are the HBM budget: a request is admitted only into
+// a free slot, so the budget is never exceeded and waiting requests queue on
+// the host (or are refused with GF2X_EAGAIN when the host queue is full).
+//
+// Loop of the scheduler thread:
+//   1. retire: every busy slot whose completion event has fired hands its
+//      results back (pinned -> caller's buffer) and stamps the completion time;
+//   2. launch: if a slot is free and requests whose arrival time has passed
+//      are waiting, pack up to max_batch of them (descriptors, a, b) into the
+//      slot's pinned buffer, copy to the device, launch one batched kernel per
+//      size class present, copy the results back, record the event.
+// While one slot's batch runs, the next arrivals form the next batch on
+// another slot: new requests join while earlier ones are on the GPU, and
+// batches on different streams overlap on the device.
+//
+// Each request carries its scheduled arrival time; it is not admitted before
+// it, so an open-loop arrival process can be replayed exactly and latency is
+// measured from the scheduled arrival to the completion stamp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "gf2x.h"
+#include "gf2x_ctx.hpp"
+#include "gf2x_internal.hpp"
+
+using namespace gf2x;
+
+namespace {
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Request {
+    uint32_t n;
+    const uint64_t *a, *b;
+    uint64_t *c;
+    uint64_t arrival_ns;
+    uint64_t ticket;
+};
+
+constexpr int kSubStreams = 6;  // one per size class present in a batch
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    hipStream_t sub[kSubStreams] = {};   // class groups of one batch run side by side
+    hipEvent_t fork = nullptr, join[kSubStreams] = {};
+    char *host = nullptr;   // pinned: [items | a | b | c]
+    char *dev = nullptr;    // device: same layout
+    std::vector<Request> reqs;
+    std::vector<uint64_t> c_off;  // word offset of each request's result in the c region
+    size_t c_region = 0;          // byte offset of the c region
+    size_t c_bytes = 0;
+    bool busy = false;
+};
+
+}  // namespace
+
+struct gf2x_srv {
+    gf2x_ctx *ctx = nullptr;
+    uint32_t max_bits = 0, max_batch = 0, max_pending = 0;
+    size_t slot_bytes = 0;
+    std::vector<Slot> slots;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Request> pending;
+    std::vector<uint64_t> done_ns;  // per ticket; 0 = not done
+    std::atomic<uint64_t> completed{0};
+    uint64_t next_ticket = 0;
+    std::atomic<bool> stop{false};
+    std::thread thread;
+    int error = GF2X_OK;
+    std::string error_text;
+    gf2x_srv_stats stats{};
+};
+
+namespace {
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Run f(i) for i in [0, count), split over up to 8 host threads when the
+// batch is large enough for the thread start-up to pay off.
+template <class F>
+void parallel_for(uint32_t count, F f) {
+    const uint32_t threads = count >= 512 ? std::min<uint32_t>(8, count / 256) : 1;
+    if (threads <= 1) {
+        for (uint32_t i = 0; i < count; ++i) f(i);
+        return;
+    }
+    std::vector<std::thread> pool;
+    const uint32_t chunk = (count + threads - 1) / threads;
+    for (uint32_t t = 0; t < threads; ++t)
+        pool.emplace_back([&, t] {
+            const uint32_t lo = t * chunk, hi = std::min(count, lo + chunk);
+            for (uint32_t i = lo; i < hi; ++i) f(i);
+        });
+    for (auto &th : pool) th.join();
+}
+
+// Retire finished batches; returns the number of requests completed.
+size_t retire(gf2x_srv *srv) {
+    size_t done = 0;
+    for (Slot &sl : srv->slots) {
+        if (!sl.busy) continue;
+        const hipError_t q = hipEventQuery(sl.done);
+        if (q == hipErrorNotReady) continue;
+        const uint64_t t = now_ns();
+        if (q != hipSuccess) {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->error = GF2X_EDEVICE;
+            srv->error_text = hipGetErrorName(q);
+        }
+        parallel_for((uint32_t)sl.reqs.size(), [&](uint32_t i) {
+            const Request &r = sl.reqs[i];
+            const uint64_t W = (r.n + 63u) / 64u;
+            std::memcpy(r.c, sl.host + sl.c_region + sl.c_off[i] * 8, W * 8);
+        });
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            for (const Request &r : sl.reqs) srv->done_ns[r.ticket] = t;
+            srv->completed += sl.reqs.size();
+        }
+        done += sl.reqs.size();
+        sl.reqs.clear();
+        sl.busy = false;
+    }
+    if (done) srv->cv.notify_all();
+    return done;
+}
+
+// Pack the admissible requests into a free slot and launch; returns true if a
+// batch was launched.
+bool launch(gf2x_srv *srv) {
+    Slot *sl = nullptr;
+    for (Slot &s : srv->slots)
+        if (!s.busy) {
+            sl = &s;
+            break;
+        }
+    if (!sl) return false;
+    const uint64_t t = now_ns();
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        while (!srv->pending.empty() && sl->reqs.size() < srv->max_batch && srv->pending.front().arrival_ns <= t) {
+            sl->reqs.push_back(srv->pending.front());
+            srv->pending.pop_front();
+        }
+    }
+    if (sl->reqs.empty()) return false;
+    const uint32_t count = (uint32_t)sl->reqs.size();
+    // layout: [DevItem x max_batch | a words | b words | c words]; operand and
+    // result regions sized for max_batch requests of the largest n
+    const uint64_t Wmax = (srv->max_bits + 63u) / 64u;
+    const size_t items_bytes = round_up((size_t)srv->max_batch * sizeof(DevItem), 256);
+    const size_t region = (size_t)srv->max_batch * Wmax * 8;
+    const size_t a_at = items_bytes, b_at = a_at + region, c_at = b_at + region;
+    DevItem *items = reinterpret_cast<DevItem *>(sl->host);
+    std::vector<DevItem> tmp(count);
+    sl->c_off.resize(count);
+    uint64_t off = 0;
+    for (uint32_t i = 0; i < count; ++i) {
+        const Request &r = sl->reqs[i];
+        const uint64_t W = (r.n + 63u) / 64u;
+        const int cls = srv->ctx->cls_of_w32[(r.n + 31u) / 32u];
+        tmp[i] = DevItem{r.n, kKindCyclic, (uint32_t)cls, 0u, off, off, off};
+        sl->c_off[i] = off;
+        off += W;
+    }
+    parallel_for(count, [&](uint32_t i) {
+        const Request &r = sl->reqs[i];
+        const uint64_t W = (r.n + 63u) / 64u;
+        std::memcpy(sl->host + a_at + sl->c_off[i] * 8, r.a, W * 8);
+        std::memcpy(sl->host + b_at + sl->c_off[i] * 8, r.b, W * 8);
+    });
+    // group by class (largest first) so that each class is one launch
+    std::stable_sort(tmp.begin(), tmp.end(), [](const DevItem &x, const DevItem &y) {
+        return class_info((int)x.cls).S > class_info((int)y.cls).S ||
+               (class_info((int)x.cls).S == class_info((int)y.cls).S && x.cls < y.cls);
+    });
+    std::memcpy(items, tmp.data(), count * sizeof(DevItem));
+    sl->c_region = c_at;
+    sl->c_bytes = off * 8;
+    hipError_t e = hipMemcpyAsync(sl->dev, sl->host, count * sizeof(DevItem), hipMemcpyHostToDevice, sl->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sl->dev + a_at, sl->host + a_at, off * 8, hipMemcpyHostToDevice, sl->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sl->dev + b_at, sl->host + b_at, off * 8, hipMemcpyHostToDevice, sl->stream);
+    const DevItem *d_items = reinterpret_cast<const DevItem *>(sl->dev);
+    uint64_t *dc = reinterpret_cast<uint64_t *>(sl->dev + c_at);
+    const uint64_t *da = reinterpret_cast<const uint64_t *>(sl->dev + a_at);
+    const uint64_t *db = reinterpret_cast<const uint64_t *>(sl->dev + b_at);
+    // one launch per class group; with several groups they go to the slot's
+    // sub-streams (forked after the copies, joined before the copy back), a
+    // single group runs on the slot's stream
+    int groups = 0;
+    for (uint32_t i = 0; i < count; ++i) groups += (i == 0 || tmp[i].cls != tmp[i - 1].cls);
+    const bool fork = groups > 1;
+    if (e == hipSuccess && fork) e = hipEventRecord(sl->fork, sl->stream);
+    uint32_t first = 0;
+    int g = 0;
+    while (e == hipSuccess && first < count) {
+        uint32_t last = first;
+        while (last < count && tmp[last].cls == tmp[first].cls) ++last;
+        hipStream_t sub = fork ? sl->sub[g % kSubStreams] : sl->stream;
+        if (fork && g < kSubStreams) e = hipStreamWaitEvent(sub, sl->fork, 0);
+        if (e == hipSuccess)
+            e = launch_batched((int)tmp[first].cls, d_items + first, last - first, dc, da, db, srv->ctx->num_cu, sub);
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->stats.launches++;
+        }
+        first = last;
+        ++g;
+    }
+    for (int k = 0; fork && e == hipSuccess && k < std::min(g, kSubStreams); ++k) {
+        e = hipEventRecord(sl->join[k], sl->sub[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sl->stream, sl->join[k], 0);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sl->host + c_at, sl->dev + c_at, off * 8, hipMemcpyDeviceToHost, sl->stream);
+    if (e == hipSuccess) e = hipEventRecord(sl->done, sl->stream);
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->error = GF2X_EDEVICE;
+        srv->error_text = hipGetErrorName(e);
+    }
+    sl->busy = true;
+    uint32_t busy = 0;
+    for (const Slot &s : srv->slots) busy += s.busy;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->stats.batches++;
+    srv->stats.admitted += count;
+    if (count > srv->stats.max_batch_seen) srv->stats.max_batch_seen = count;
+    if (busy > srv->stats.max_slots_busy) srv->stats.max_slots_busy = busy;
+    return true;
+}
+
+void scheduler(gf2x_srv *srv) {
+    hipSetDevice(srv->ctx->device);
+    while (true) {
+        const size_t done = retire(srv);
+        const bool launched = launch(srv);
+        if (srv->stop.load()) {
+            bool busy = false;
+            for (const Slot &s : srv->slots) busy |= s.busy;
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (!busy && srv->pending.empty()) break;
+        }
+        if (!done && !launched) {
+            // idle: wait for the next arrival, a completion or a new submission
+            uint64_t wait_ns = 20000;
+            {
+                std::unique_lock<std::mutex> lk(srv->mu);
+                if (!srv->pending.empty()) {
+                    const uint64_t t = now_ns(), a = srv->pending.front().arrival_ns;
+                    if (a > t) wait_ns = std::min<uint64_t>(wait_ns, a - t);
+                }
+                bool any_busy = false;
+                for (const Slot &s : srv->slots) any_busy |= s.busy;
+                if (any_busy) wait_ns = std::min<uint64_t>(wait_ns, 5000);
+                if (wait_ns > 2000) srv->cv.wait_for(lk, std::chrono::nanoseconds(wait_ns));
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+uint64_t gf2x_srv_now_ns(void) { return now_ns(); }
+
+int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
+    if (!out || !ctx) return GF2X_EINVAL;
+    *out = nullptr;
+    gf2x_srv_opts o{};
+    if (opts) o = *opts;
+    if (o.flags != 0) return GF2X_EINVAL;
+    const size_t budget = o.hbm_budget_bytes ? o.hbm_budget_bytes : ((size_t)256 << 20);
+    const uint32_t streams = o.streams ? o.streams : 4;
+    const uint32_t max_bits = o.max_bits ? o.max_bits : 57637;
+    if (streams > 16 || max_bits > kMaxBits) return GF2X_EINVAL;
+    const uint64_t Wmax = (max_bits + 63u) / 64u;
+    const size_t per_req = sizeof(DevItem) + 3 * Wmax * 8;
+    uint64_t max_batch = budget / streams / per_req;
+    if (o.max_batch && o.max_batch < max_batch) max_batch = o.max_batch;
+    if (max_batch < 1) return GF2X_ENOMEM;  // the budget cannot hold one request per stream
+    gf2x_srv *srv = new (std::nothrow) gf2x_srv();
+    if (!srv) return GF2X_ENOMEM;
+    srv->ctx = ctx;
+    srv->max_bits = max_bits;
+    srv->max_batch = (uint32_t)std::min<uint64_t>(max_batch, 1u << 20);
+    srv->max_pending = o.max_pending ? o.max_pending : (1u << 22);
+    srv->slot_bytes = round_up((size_t)srv->max_batch * sizeof(DevItem), 256) + 3 * (size_t)srv->max_batch * Wmax * 8;
+    srv->slots.resize(streams);
+    hipError_t e = hipSetDevice(ctx->device);
+    for (Slot &sl : srv->slots) {
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.fork, hipEventDisableTiming);
+        for (int k = 0; k < kSubStreams && e == hipSuccess; ++k) {
+            e = hipStreamCreateWithFlags(&sl.sub[k], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.join[k], hipEventDisableTiming);
+        }
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.host), srv->slot_bytes, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.dev), srv->slot_bytes);
+    }
+    if (e != hipSuccess) {
+        gf2x_srv_destroy(srv);
+        return e == hipErrorOutOfMemory ? GF2X_ENOMEM : GF2X_EDEVICE;
+    }
+    srv->stats.max_batch = srv->max_batch;
+    srv->stats.hbm_bytes = srv->slot_bytes * streams;
+    srv->thread = std::thread(scheduler, srv);
+    *out = srv;
+    return GF2X_OK;
+}
+
+int gf2x_srv_submit(gf2x_srv *srv, uint32_t count, const uint32_t *n_bits, const uint64_t *a_base,
+                    const uint64_t *a_off, const uint64_t *b_base, const uint64_t *b_off, uint64_t *c_base,
+                    const uint64_t *c_off, const uint64_t *arrival_ns, uint64_t *first_ticket) {
+    if (!srv || !first_ticket || (count && (!n_bits || !a_base || !a_off || !b_base || !b_off || !c_base || !c_off)))
+        return GF2X_EINVAL;
+    for (uint32_t i = 0; i < count; ++i)
+        if (n_bits[i] == 0 || n_bits[i] > srv->max_bits) return GF2X_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->error) return srv->error;
+        if (srv->pending.size() + count > srv->max_pending) {
+            srv->stats.refused += count;
+            return GF2X_EAGAIN;
+        }
+        *first_ticket = srv->next_ticket;
+        const uint64_t t = now_ns();
+        srv->done_ns.resize(srv->next_ticket + count, 0);
+        for (uint32_t i = 0; i < count; ++i) {
+            Request r{n_bits[i], a_base + a_off[i], b_base + b_off[i], c_base + c_off[i],
+                      arrival_ns ? arrival_ns[i] : t, srv->next_ticket++};
+            srv->pending.push_back(r);
+        }
+        srv->stats.submitted += count;
+    }
+    srv->cv.notify_all();
+    return GF2X_OK;
+}
+
+int gf2x_srv_completion(gf2x_srv *srv, uint64_t first_ticket, uint32_t count, uint64_t *done_ns) {
+    if (!srv || (count && !done_ns)) return GF2X_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    if (first_ticket + count > srv->done_ns.size()) return GF2X_EINVAL;
+    for (uint32_t i = 0; i < count; ++i) done_ns[i] = srv->done_ns[first_ticket + i];
+    return srv->error;
+}
+
+int gf2x_srv_drain(gf2x_srv *srv, uint64_t timeout_ms) {
+    if (!srv) return GF2X_EINVAL;
+    std::unique_lock<std::mutex> lk(srv->mu);
+    const bool ok = srv->cv.wait_for(lk, std::chrono::milliseconds(timeout_ms ? timeout_ms : 3600000ull), [&] {
+        return srv->error != GF2X_OK || srv->completed.load() == srv->next_ticket;
+    });
+    if (srv->error) return srv->error;
+    return ok ? GF2X_OK : GF2X_EAGAIN;
+}
+
+int gf2x_srv_get_stats(gf2x_srv *srv, gf2x_srv_stats *st) {
+    if (!srv || !st) return GF2X_EINVAL;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    *st = srv->stats;
+    st->completed = srv->completed.load();
+    st->pending = srv->pending.size();
+    return GF2X_OK;
+}
+
+void gf2x_srv_destroy(gf2x_srv *srv) {
+    if (!srv) return;
+    if (srv->thread.joinable()) {
+        srv->stop = true;
+        srv->cv.notify_all();
+        srv->thread.join();
+    }
+    for (Slot &sl : srv->slots) {
+        if (sl.stream) hipStreamSynchronize(sl.stream);
+        if (sl.dev) hipFree(sl.dev);
+        if (sl.host) hipHostFree(sl.host);
+        if (sl.done) hipEventDestroy(sl.done);
+        if (sl.fork) hipEventDestroy(sl.fork);
+        for (int k = 0; k < kSubStreams; ++k) {
+            if (sl.sub[k]) hipStreamSynchronize(sl.sub[k]);
+            if (sl.sub[k]) hipStreamDestroy(sl.sub[k]);
+            if (sl.join[k]) hipEventDestroy(sl.join[k]);
+        }
+        if (sl.stream) hipStreamDestroy(sl.stream);
+    }
+    delete srv;
+}
+
+}  // extern "C"

@@ -20,6 +20,7 @@ GF2X_OK = 0
 GF2X_EINVAL = -1
 GF2X_ENOMEM = -2
 GF2X_EDEVICE = -3
+GF2X_EAGAIN = -4
 GF2X_ENOTSUP = -5
 GF2X_MAX_BITS = 131072
 
@@ -59,6 +60,36 @@ class _Opts(ctypes.Structure):
     ]
 
 
+class _SrvOpts(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_size_t),
+        ("streams", ctypes.c_uint32),
+        ("max_bits", ctypes.c_uint32),
+        ("max_batch", ctypes.c_uint32),
+        ("max_pending", ctypes.c_uint32),
+        ("flags", ctypes.c_uint32),
+    ]
+
+
+class SrvStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_uint64),
+        ("admitted", ctypes.c_uint64),
+        ("completed", ctypes.c_uint64),
+        ("refused", ctypes.c_uint64),
+        ("pending", ctypes.c_uint64),
+        ("batches", ctypes.c_uint64),
+        ("launches", ctypes.c_uint64),
+        ("max_batch", ctypes.c_uint32),
+        ("max_batch_seen", ctypes.c_uint32),
+        ("max_slots_busy", ctypes.c_uint32),
+        ("hbm_bytes", ctypes.c_uint64),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 def load():
     """Load the built library (raises if it is missing: no fallback path)."""
     global _lib
@@ -68,6 +99,15 @@ def load():
         raise RuntimeError(
             "libgf2x.so is not built (expected at %s); run __graft_entry__.build()" % LIB_PATH
         )
+    # torch bundles its own HIP runtime under the same soname as the system
+    # one.  Importing torch first makes the library bind to that runtime, so
+    # the process has one HIP runtime and torch's device pointers and streams
+    # are valid in the library.  (Loaded the other way round, two runtimes
+    # would compete for the device.)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     vp, u32, u64, sz = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t
     lib.gf2x_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(_Opts)]
@@ -86,6 +126,20 @@ def load():
     lib.gf2x_schedule_info.restype = ctypes.c_int
     lib.gf2x_tune.argtypes = [vp, ctypes.POINTER(u32), u32, u32, ctypes.c_char_p]
     lib.gf2x_tune.restype = ctypes.c_int
+    lib.gf2x_srv_create.argtypes = [ctypes.POINTER(vp), vp, ctypes.POINTER(_SrvOpts)]
+    lib.gf2x_srv_create.restype = ctypes.c_int
+    lib.gf2x_srv_submit.argtypes = [vp, u32, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.POINTER(u64)]
+    lib.gf2x_srv_submit.restype = ctypes.c_int
+    lib.gf2x_srv_completion.argtypes = [vp, u64, u32, vp]
+    lib.gf2x_srv_completion.restype = ctypes.c_int
+    lib.gf2x_srv_drain.argtypes = [vp, u64]
+    lib.gf2x_srv_drain.restype = ctypes.c_int
+    lib.gf2x_srv_get_stats.argtypes = [vp, ctypes.POINTER(SrvStats)]
+    lib.gf2x_srv_get_stats.restype = ctypes.c_int
+    lib.gf2x_srv_now_ns.argtypes = []
+    lib.gf2x_srv_now_ns.restype = u64
+    lib.gf2x_srv_destroy.argtypes = [vp]
+    lib.gf2x_srv_destroy.restype = None
     lib.gf2x_strerror.argtypes = [ctypes.c_int]
     lib.gf2x_strerror.restype = ctypes.c_char_p
     lib.gf2x_last_device_error.argtypes = []
@@ -207,6 +261,75 @@ class Context:
             "gf2x_schedule_info",
         )
         return s.value, base.value, ops.value, name.value.decode()
+
+
+class Server:
+    """Continuous-batching server over a Context (gf2x_srv_* in the C ABI).
+    Operands and results are host numpy uint64 arrays with word offsets; the
+    server keeps references to them until drain() returns."""
+
+    def __init__(self, ctx, hbm_budget_bytes=0, streams=0, max_bits=0, max_batch=0, max_pending=0):
+        self._lib = load()
+        self._ctx = ctx
+        opts = _SrvOpts(hbm_budget_bytes, streams, max_bits, max_batch, max_pending, 0)
+        h = ctypes.c_void_p()
+        _check(self._lib.gf2x_srv_create(ctypes.byref(h), ctx._h, ctypes.byref(opts)), "gf2x_srv_create")
+        self._h = h
+        self._keep = []
+
+    def now_ns(self):
+        return self._lib.gf2x_srv_now_ns()
+
+    def submit(self, n_bits, a, a_off, b, b_off, c, c_off, arrival_ns=None):
+        """Queue requests; returns the first ticket (tickets are consecutive)."""
+        arrs = [np.ascontiguousarray(n_bits, dtype=np.uint32)]
+        for x in (a_off, b_off, c_off):
+            arrs.append(np.ascontiguousarray(x, dtype=np.uint64))
+        arr_ns = None if arrival_ns is None else np.ascontiguousarray(arrival_ns, dtype=np.uint64)
+        for buf in (a, b, c):
+            if buf.dtype != np.uint64 or not buf.flags.c_contiguous:
+                raise ValueError("operand and result buffers must be contiguous uint64 arrays")
+        count = len(arrs[0])
+        first = ctypes.c_uint64()
+        rc = self._lib.gf2x_srv_submit(
+            self._h, count, arrs[0].ctypes.data, a.ctypes.data, arrs[1].ctypes.data, b.ctypes.data,
+            arrs[2].ctypes.data, c.ctypes.data, arrs[3].ctypes.data,
+            None if arr_ns is None else arr_ns.ctypes.data, ctypes.byref(first))
+        _check(rc, "gf2x_srv_submit")
+        self._keep.append((arrs, arr_ns, a, b, c))
+        return first.value
+
+    def completion(self, first, count):
+        out = np.zeros(count, dtype=np.uint64)
+        _check(self._lib.gf2x_srv_completion(self._h, first, count, out.ctypes.data), "gf2x_srv_completion")
+        return out
+
+    def drain(self, timeout_ms=0):
+        _check(self._lib.gf2x_srv_drain(self._h, timeout_ms), "gf2x_srv_drain")
+        self._keep = []
+
+    def stats(self):
+        st = SrvStats()
+        _check(self._lib.gf2x_srv_get_stats(self._h, ctypes.byref(st)), "gf2x_srv_get_stats")
+        return st.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.gf2x_srv_destroy(self._h)
+            self._h = None
+            self._keep = []
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def make_items(n_bits, kinds, a_off, b_off, c_off):

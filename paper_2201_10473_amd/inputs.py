@@ -84,6 +84,18 @@ def dense_batch(n, count, seed, role=0, first_item=0):
     return out
 
 
+def dense_items(n, item_ids, seed, role=0):
+    """(len(item_ids), words(n)); row r is ``dense(n, seed, item_ids[r], role)``."""
+    W = words(n)
+    ids = np.asarray(item_ids, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        keys = (np.uint64(int(seed) << 24 & 0xFFFFFFFFFFFFFFFF) ^ (ids << np.uint64(2))) ^ np.uint64(role)
+        k = np.arange(1, W + 1, dtype=np.uint64)
+        out = _finalise(keys[:, None] + k[None, :] * GAMMA)
+    out[:, -1] &= top_mask(n)
+    return out
+
+
 def sparse_positions(n, weight, seed, item=0, role=2):
     """``weight`` distinct positions in [0, n), uniform, by rejection sampling.
 

@@ -72,3 +72,12 @@ def test_schedule_for_ring_sizes_is_subquadratic(n):
     # far fewer base products than the w32^2 of a word schoolbook
     assert base < 0.3 * w32 * w32
     assert "T3" in name or "K2" in name
+
+
+def test_server_rejects_null_context():
+    lib = gf2x.load()
+    h = ctypes.c_void_p()
+    assert lib.gf2x_srv_create(ctypes.byref(h), None, None) == gf2x.GF2X_EINVAL
+    assert lib.gf2x_srv_drain(None, 1) == gf2x.GF2X_EINVAL
+    assert lib.gf2x_srv_now_ns() > 0
+    lib.gf2x_srv_destroy(None)

@@ -1,0 +1,141 @@
+"""The serving loop (continuous batching under an HBM budget) and the mixed
+workload: every served result equals the same product computed alone and in
+a plain batched launch, sampled results equal the oracle, and the admission
+limits hold."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_10473_amd import gf2x, inputs, serve
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gf2x.Context(0)
+    yield c
+    c.close()
+
+
+def _alone(ctx, n, a, b):
+    import torch
+    from tests.gpu_util import empty_dev, from_dev, to_dev
+    C = empty_dev(len(a))
+    ctx.mul_cyclic(C, to_dev(a), to_dev(b), n)
+    torch.cuda.synchronize()
+    return from_dev(C)
+
+
+def test_served_equals_alone_batched_and_oracle(ctx):
+    print("case serving rate=50000 count=3000", flush=True)
+    res, (ns, off, A, B, C) = serve.run(ctx, 50000, 3000, inputs.SEED_BASE + 5)
+    assert res["server"]["completed"] == 3000 and res["server"]["admitted"] == 3000
+    assert serve.check_against_batched(ctx, ns, off, A, B, C) == 3000
+    rng = np.random.default_rng(0)
+    for i in rng.choice(3000, 30, replace=False):  # 1% re-run alone
+        n = int(ns[i])
+        W = (n + 63) // 64
+        sl = slice(int(off[i]), int(off[i]) + W)
+        assert np.array_equal(_alone(ctx, n, A[sl], B[sl]), C[sl]), i
+    for i in (0, 1, 2999):
+        n = int(ns[i])
+        W = (n + 63) // 64
+        sl = slice(int(off[i]), int(off[i]) + W)
+        assert np.array_equal(C[sl], oracle.mul_cyclic(A[sl], B[sl], n)), i
+    # latencies are measured from scheduled arrival and are positive
+    assert res["p50_us"] > 0 and res["p99_us"] >= res["p50_us"]
+
+
+def test_high_rate_batches_overlap(ctx):
+    print("case serving rate=500000 count=20000", flush=True)
+    res, bufs = serve.run(ctx, 500000, 20000, inputs.SEED_BASE + 6)
+    st = res["server"]
+    assert st["completed"] == 20000
+    assert st["max_batch_seen"] > 1          # arrivals joined running work as batches
+    assert st["max_slots_busy"] >= 2         # batches on different streams in flight together
+    serve.check_against_batched(ctx, *bufs)
+
+
+def test_tiny_hbm_budget_backpressure(ctx):
+    """A budget of one largest request per stream: every batch holds one
+    request, nothing is dropped, results are unchanged."""
+    W = (57637 + 63) // 64
+    per_req = 40 + 3 * W * 8
+    print("case serving tiny budget", flush=True)
+    res, bufs = serve.run(ctx, 200000, 400, inputs.SEED_BASE + 7, hbm_budget_bytes=4 * per_req, streams=4,
+                          warm=False)
+    st = res["server"]
+    assert st["max_batch"] == 1 and st["max_batch_seen"] == 1
+    assert st["completed"] == 400 and st["batches"] == 400
+    assert st["hbm_bytes"] <= 4 * per_req + 4 * 256
+    serve.check_against_batched(ctx, *bufs)
+
+
+def test_budget_too_small_and_queue_full(ctx):
+    with pytest.raises(gf2x.Gf2xError) as e:
+        gf2x.Server(ctx, hbm_budget_bytes=1000, streams=4)
+    assert e.value.code == gf2x.GF2X_ENOMEM
+    ns, off, A, B = serve.make_requests(12, 3)
+    C = np.zeros_like(A)
+    far = None
+    with gf2x.Server(ctx, max_pending=10) as srv:
+        far = np.full(12, srv.now_ns() + int(50e6), dtype=np.uint64)  # 50 ms in the future
+        with pytest.raises(gf2x.Gf2xError) as e:
+            srv.submit(ns, A, off, B, off, C, off, far)
+        assert e.value.code == gf2x.GF2X_EAGAIN
+        first = srv.submit(ns[:10], A, off[:10], B, off[:10], C, off[:10], far[:10])
+        srv.drain()
+        done = srv.completion(first, 10)
+        assert (done >= far[:10]).all()      # nothing admitted before its arrival time
+        assert srv.stats()["refused"] == 12
+    with pytest.raises(gf2x.Gf2xError):
+        gf2x.Server(ctx, max_bits=gf2x.GF2X_MAX_BITS + 1)
+
+
+def test_mixed_workload_graph(ctx):
+    """The mixed workload: 8192 products, n uniform over the six sizes, half
+    dense x sparse, in one graph-captured launch sequence; parity invariant
+    on every item, oracle and rotation closed form on samples."""
+    import torch
+    from tests import brute
+    from tests.gpu_util import empty_dev, from_dev, parity_rows, to_dev
+    count = 8192
+    seed = inputs.SEED_BASE + 4
+    ns, off, A, B = serve.make_requests(count, seed)
+    sparse_items = np.arange(1, count, 2)
+    pos_of = {}
+    for i in sparse_items[:64]:  # sparse operands for the first 64 odd items, kept for the closed form
+        n = int(ns[i])
+        pos = inputs.sparse_positions(n, inputs.sparse_weight_for(n), seed, int(i))
+        pos_of[int(i)] = pos
+    for i in sparse_items:
+        n = int(ns[i])
+        W = (n + 63) // 64
+        pos = pos_of.get(int(i)) or inputs.sparse_positions(n, inputs.sparse_weight_for(n), seed, int(i))
+        B[int(off[i]):int(off[i]) + W] = inputs.from_positions(n, pos)
+    items = gf2x.make_items(ns, gf2x.KIND_CYCLIC, off, off, off)
+    dA, dB, dC = to_dev(A), to_dev(B), empty_dev(len(A))
+    for _ in range(2):
+        ctx.mul_batched(items, dC, dA, dB, gf2x.USE_GRAPH)
+        torch.cuda.synchronize()
+    C = from_dev(dC)
+    for n in inputs.RING_SIZES:
+        idx = np.nonzero(ns == n)[0]
+        W = (n + 63) // 64
+        rows = lambda X: X[(off[idx][:, None] + np.arange(W)[None, :]).astype(np.int64)]
+        assert np.array_equal(parity_rows(rows(C)), parity_rows(rows(A)) & parity_rows(rows(B)))
+    for i in list(range(0, 12)) + [count - 1]:
+        n = int(ns[i])
+        W = (n + 63) // 64
+        sl = slice(int(off[i]), int(off[i]) + W)
+        assert np.array_equal(C[sl], oracle.mul_cyclic(A[sl], B[sl], n)), i
+    for i, pos in list(pos_of.items())[:16]:
+        n = int(ns[i])
+        W = (n + 63) // 64
+        sl = slice(int(off[i]), int(off[i]) + W)
+        xa = brute.words_to_int(A[sl])
+        expect = 0
+        for q in pos:
+            expect ^= brute.rotate(xa, q, n)
+        assert brute.words_to_int(C[sl]) == expect, i
