@@ -162,24 +162,73 @@ int ensure_forks(gf2x_ctx *ctx) {
     return GF2X_OK;
 }
 
+// Workspace bytes of the staged groups of a launch (each group gets its own
+// region, since groups may run concurrently).
+size_t staged_bytes(const std::vector<Group> &groups) {
+    size_t total = 0;
+    for (const Group &g : groups) total += (staged_workspace_bytes(g.cls, g.count) + 255) / 256 * 256;
+    return total;
+}
+
+// Grow a workspace owned by the context (ws/ws_bytes) to `need` bytes within
+// the budget; the old buffer is freed after the device is done with it.
+int ensure_ws(gf2x_ctx *ctx, void *&ws, size_t &ws_bytes, size_t need, hipEvent_t guard, bool guard_used) {
+    if (need <= ws_bytes) return GF2X_OK;
+    if (ctx->allocated - ws_bytes + need > ctx->budget) return GF2X_ENOMEM;
+    if (ws) {
+        if (guard_used) HIP_TRY(hipEventSynchronize(guard));
+        HIP_TRY(hipFree(ws));
+        ctx->allocated -= ws_bytes;
+        ws = nullptr;
+        ws_bytes = 0;
+    }
+    if (hipMalloc(&ws, need) != hipSuccess) return GF2X_ENOMEM;
+    ws_bytes = need;
+    ctx->allocated += need;
+    return GF2X_OK;
+}
+
+// Staged groups whose workspace does not fit the budget run their direct class.
+void fit_staged(gf2x_ctx *ctx, std::vector<Group> &groups, size_t have) {
+    size_t total = staged_bytes(groups);
+    const size_t avail = ctx->budget > ctx->allocated ? ctx->budget - ctx->allocated + have : have;
+    for (Group &g : groups) {
+        if (total <= avail) break;
+        if (class_info(g.cls).child >= 0) {
+            total -= (staged_workspace_bytes(g.cls, g.count) + 255) / 256 * 256;
+            g.cls = class_info(g.cls).direct;
+        }
+    }
+}
+
+int launch_one(gf2x_ctx *ctx, const Group &g, const DevItem *d_items, char *&ws, uint64_t *c, const uint64_t *a,
+               const uint64_t *b, hipStream_t s) {
+    hipError_t e;
+    if (class_info(g.cls).child >= 0) {
+        e = launch_staged(g.cls, d_items + g.first, g.count, c, a, b, ws, ctx->num_cu, s);
+        ws += (staged_workspace_bytes(g.cls, g.count) + 255) / 256 * 256;
+    } else {
+        e = launch_batched(g.cls, d_items + g.first, g.count, c, a, b, ctx->num_cu, s);
+    }
+    return e == hipSuccess ? GF2X_OK : device_error(e);
+}
+
 // One launch per class group.  A single group goes straight onto s; several
 // groups are spread over the context's internal streams, forked from s and
-// joined back to it with events, so that different sizes overlap.
+// joined back to it with events, so that different sizes overlap.  Staged
+// groups carve their regions out of ws in group order.
 int launch_groups(gf2x_ctx *ctx, const DevItem *d_items, const std::vector<Group> &groups, uint64_t *c,
-                  const uint64_t *a, const uint64_t *b, hipStream_t s) {
-    if (groups.size() == 1) {
-        const Group &g = groups[0];
-        hipError_t e = launch_batched(g.cls, d_items + g.first, g.count, c, a, b, ctx->num_cu, s);
-        return e == hipSuccess ? GF2X_OK : device_error(e);
-    }
+                  const uint64_t *a, const uint64_t *b, void *ws, hipStream_t s) {
+    char *wp = reinterpret_cast<char *>(ws);
+    if (groups.size() == 1) return launch_one(ctx, groups[0], d_items, wp, c, a, b, s);
     int rc = ensure_forks(ctx);
     if (rc) return rc;
     const int K = std::min<int>(gf2x_ctx::kForks, (int)groups.size());
     HIP_TRY(hipEventRecord(ctx->fork_event[gf2x_ctx::kForks], s));
     for (int k = 0; k < K; ++k) HIP_TRY(hipStreamWaitEvent(ctx->fork_stream[k], ctx->fork_event[gf2x_ctx::kForks], 0));
     for (size_t i = 0; i < groups.size(); ++i) {
-        const Group &g = groups[i];
-        HIP_TRY(launch_batched(g.cls, d_items + g.first, g.count, c, a, b, ctx->num_cu, ctx->fork_stream[i % K]));
+        rc = launch_one(ctx, groups[i], d_items, wp, c, a, b, ctx->fork_stream[i % K]);
+        if (rc) return rc;
     }
     for (int k = 0; k < K; ++k) {
         HIP_TRY(hipEventRecord(ctx->fork_event[k], ctx->fork_stream[k]));
@@ -234,7 +283,7 @@ int gf2x_create(gf2x_ctx **out, const gf2x_opts *opts) {
     default_table(ctx);
     if (o.tune_cache) load_tune_cache(ctx, o.tune_cache);
     uint8_t tab[kMaxWords32 + 1];
-    for (uint32_t w = 0; w <= kMaxWords32; ++w) tab[w] = (uint8_t)ctx->cls_of_w32[w];
+    for (uint32_t w = 0; w <= kMaxWords32; ++w) tab[w] = (uint8_t)class_info(ctx->cls_of_w32[w]).direct;
     e = hipMalloc(&ctx->d_cls, sizeof tab);
     if (e == hipSuccess) e = hipMemcpy(ctx->d_cls, tab, sizeof tab, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -253,7 +302,9 @@ void gf2x_destroy(gf2x_ctx *ctx) {
         if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
         if (kv.second.graph) hipGraphDestroy(kv.second.graph);
         if (kv.second.items) hipFree(kv.second.items);
+        if (kv.second.staged_ws) hipFree(kv.second.staged_ws);
     }
+    if (ctx->staged_ws) hipFree(ctx->staged_ws);
     toeplitz::release(ctx->tz);
     for (int i = 0; i < gf2x_ctx::kForks; ++i)
         if (ctx->fork_stream[i]) hipStreamDestroy(ctx->fork_stream[i]);
@@ -270,7 +321,7 @@ int gf2x_mul(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b, u
     int rc = check_single(ctx, c, a, b, n_bits, 2 * words64(n_bits));
     if (rc) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
-    const int cls = ctx->cls_of_w32[(n_bits + 31u) / 32u];
+    const int cls = class_info(ctx->cls_of_w32[(n_bits + 31u) / 32u]).direct;
     HIP_TRY(launch_single(cls, a, b, c, n_bits, kKindFull, reinterpret_cast<hipStream_t>(stream)));
     return GF2X_OK;
 }
@@ -280,7 +331,7 @@ int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_
     int rc = check_single(ctx, c, a, b, n_bits, words64(n_bits));
     if (rc) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
-    const int cls = ctx->cls_of_w32[(n_bits + 31u) / 32u];
+    const int cls = class_info(ctx->cls_of_w32[(n_bits + 31u) / 32u]).direct;
     HIP_TRY(launch_single(cls, a, b, c, n_bits, kKindCyclic, reinterpret_cast<hipStream_t>(stream)));
     return GF2X_OK;
 }
@@ -339,15 +390,27 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
         const uint64_t sum = checksum(items, count);
         auto it = ctx->graphs.find(key);
         if (it != ctx->graphs.end() && it->second.checksum != sum) {
+            HIP_TRY(hipStreamSynchronize(s));  // the old graph may still be running on s
             hipGraphExecDestroy(it->second.exec);
             hipGraphDestroy(it->second.graph);
             hipFree(it->second.items);
+            if (it->second.staged_ws) {
+                hipFree(it->second.staged_ws);
+                ctx->allocated -= it->second.staged_bytes;
+            }
             ctx->graphs.erase(it);
             it = ctx->graphs.end();
         }
         if (it == ctx->graphs.end()) {
             GraphEntry g;
             g.checksum = sum;
+            fit_staged(ctx, groups, 0);
+            const size_t sb = staged_bytes(groups);
+            if (sb) {
+                if (hipMalloc(&g.staged_ws, sb) != hipSuccess) return GF2X_ENOMEM;
+                g.staged_bytes = sb;
+                ctx->allocated += sb;
+            }
             if (hipMalloc(&g.items, count * sizeof(DevItem)) != hipSuccess) return GF2X_ENOMEM;
             HIP_TRY(hipMemcpyAsync(g.items, host.data(), count * sizeof(DevItem), hipMemcpyHostToDevice, s));
             // capture the launches on a private stream, ordered after the copy
@@ -355,7 +418,7 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
             HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
             hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                int lrc = launch_groups(ctx, g.items, groups, c_base, a_base, b_base, cap);
+                int lrc = launch_groups(ctx, g.items, groups, c_base, a_base, b_base, g.staged_ws, cap);
                 hipError_t e2 = hipStreamEndCapture(cap, &g.graph);
                 if (lrc) e = hipErrorLaunchFailure;
                 else e = e2;
@@ -365,6 +428,10 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
             if (e != hipSuccess) {
                 if (g.graph) hipGraphDestroy(g.graph);
                 hipFree(g.items);
+                if (g.staged_ws) {
+                    hipFree(g.staged_ws);
+                    ctx->allocated -= g.staged_bytes;
+                }
                 return device_error(e);
             }
             it = ctx->graphs.emplace(key, g).first;
@@ -375,9 +442,12 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
 
     rc = ensure_items(ctx, count);
     if (rc) return rc;
+    fit_staged(ctx, groups, ctx->staged_ws_bytes);
+    rc = ensure_ws(ctx, ctx->staged_ws, ctx->staged_ws_bytes, staged_bytes(groups), ctx->ws_free, ctx->ws_used);
+    if (rc) return rc;
     if (ctx->ws_used) HIP_TRY(hipStreamWaitEvent(s, ctx->ws_free, 0));
     HIP_TRY(hipMemcpyAsync(ctx->d_items, host.data(), count * sizeof(DevItem), hipMemcpyHostToDevice, s));
-    rc = launch_groups(ctx, ctx->d_items, groups, c_base, a_base, b_base, s);
+    rc = launch_groups(ctx, ctx->d_items, groups, c_base, a_base, b_base, ctx->staged_ws, s);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(ctx->ws_free, s));
     ctx->ws_used = true;
@@ -393,7 +463,10 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
     for (uint32_t i = 0; i < nsizes; ++i) maxn = std::max(maxn, sizes[i]);
     if (nsizes) {
         const uint64_t W = words64(maxn);
-        const size_t bytes = (size_t)batch * W * 8 * 3 + (size_t)batch * sizeof(DevItem);
+        size_t staged = 0;
+        for (int c = 0; c < kNumClasses; ++c) staged = std::max(staged, staged_workspace_bytes(c, batch));
+        const size_t main_bytes = (size_t)batch * W * 8 * 3 + (size_t)batch * sizeof(DevItem);
+        const size_t bytes = (main_bytes + 255) / 256 * 256 + staged;
         if (ctx->allocated + bytes > ctx->budget) return GF2X_ENOMEM;
         uint64_t *buf = nullptr;
         if (hipMalloc(&buf, bytes) != hipSuccess) return GF2X_ENOMEM;
@@ -405,6 +478,7 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
         if (e == hipSuccess) e = launch_fill_words(buf, (size_t)batch * W * 2, 0x2201047300ull, s);
         uint64_t *A = buf, *B = buf + (size_t)batch * W, *C = buf + (size_t)2 * batch * W;
         DevItem *d_items = reinterpret_cast<DevItem *>(buf + (size_t)3 * batch * W);
+        void *staged_ws = reinterpret_cast<char *>(buf) + (main_bytes + 255) / 256 * 256;
         std::vector<DevItem> host(batch);
         for (uint32_t i = 0; e == hipSuccess && i < nsizes; ++i) {
             const uint32_t n = sizes[i], w32 = (n + 31u) / 32u;
@@ -419,7 +493,10 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
                 float t = 0.f;
                 for (int rep = 0; e == hipSuccess && rep < 4; ++rep) {
                     e = hipEventRecord(e0, s);
-                    if (e == hipSuccess) e = launch_batched(c, d_items, batch, C, A, B, ctx->num_cu, s);
+                    if (e == hipSuccess) {
+                        if (ci.child >= 0) e = launch_staged(c, d_items, batch, C, A, B, staged_ws, ctx->num_cu, s);
+                        else e = launch_batched(c, d_items, batch, C, A, B, ctx->num_cu, s);
+                    }
                     if (e == hipSuccess) e = hipEventRecord(e1, s);
                     if (e == hipSuccess) e = hipEventSynchronize(e1);
                     float ms = 0.f;
@@ -439,7 +516,7 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e == hipSuccess) {
             uint8_t tab[kMaxWords32 + 1];
-            for (uint32_t w = 0; w <= kMaxWords32; ++w) tab[w] = (uint8_t)ctx->cls_of_w32[w];
+            for (uint32_t w = 0; w <= kMaxWords32; ++w) tab[w] = (uint8_t)class_info(ctx->cls_of_w32[w]).direct;
             e = hipMemcpy(ctx->d_cls, tab, sizeof tab, hipMemcpyHostToDevice);
         }
         if (e0) hipEventDestroy(e0);

@@ -17,6 +17,8 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     DevItem *items = nullptr;  // private copy of the descriptors
+    void *staged_ws = nullptr; // private workspace of the staged groups
+    size_t staged_bytes = 0;
     uint64_t checksum = 0;
 };
 
@@ -31,7 +33,9 @@ struct gf2x_ctx {
     uint8_t *d_cls = nullptr;      // device copy of cls_of_w32
     gf2x::DevItem *d_items = nullptr;    // workspace for host item descriptors
     size_t d_items_cap = 0;
-    hipEvent_t ws_free = nullptr;  // recorded after the last launch reading d_items
+    hipEvent_t ws_free = nullptr;  // recorded after the last launch reading d_items / staged_ws
+    void *staged_ws = nullptr;     // workspace of staged classes (point operands and products)
+    size_t staged_ws_bytes = 0;
     bool ws_used = false;
     std::map<std::tuple<const void *, uint32_t, const void *, const void *, const void *, uint32_t, void *>,
              gf2x::GraphEntry>

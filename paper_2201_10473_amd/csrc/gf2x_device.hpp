@@ -477,6 +477,48 @@ struct SeqT3 {
         __syncthreads();
     }
 
+    // Interpolation only: the five point products (2*S1 words each, in order
+    // 0, 1, x, x+1, inf) were computed elsewhere and sit at products (any
+    // address space).  scratch needs INTERP_SCRATCH words; returns the 2S-word
+    // product inside scratch.
+    static constexpr int INTERP_SCRATCH = R_WORDS + SA_WORDS + UA_WORDS + TMP_WORDS;
+    __device__ __forceinline__ static u32 *interp_from(const u32 *products, u32 *scratch) {
+        u32 *R = scratch;
+        u32 *Sa = R + R_WORDS;
+        u32 *Ua = Sa + SA_WORDS;
+        u32 *tmp = Ua + UA_WORDS;
+        for (int k = threadIdx.x; k < R_WORDS + SA_WORDS + UA_WORDS; k += NT) R[k] = 0;
+        __syncthreads();
+        absorb<0>(products + 0 * 2 * S1, R, Sa, Ua);
+        __syncthreads();
+        absorb<1>(products + 1 * 2 * S1, R, Sa, Ua);
+        __syncthreads();
+        absorb<2>(products + 2 * 2 * S1, R, Sa, Ua);
+        __syncthreads();
+        absorb<3>(products + 3 * 2 * S1, R, Sa, Ua);
+        __syncthreads();
+        absorb<4>(products + 4 * 2 * S1, R, Sa, Ua);
+        __syncthreads();
+        div_xx1_pair<2 * m>(Sa, Ua, tmp);
+        auto c3 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Sa[j] : 0u; };
+        auto c2 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Ua[j] : 0u; };
+        par_map<R_WORDS>(R, [&](int r) -> u32 { return R[r] ^ c2(r - m) ^ c2(r - 2 * m) ^ c3(r - m) ^ c3(r - 3 * m); });
+        __syncthreads();
+        return R;
+    }
+
+    // Word w of operand x of point e, from a source of the parent's words.
+    template <class Part>
+    __device__ __forceinline__ static u32 point_word(int e, int x, int w, const Part &part) {
+        switch (e) {
+            case 0: return part(x, 0, w);
+            case 1: return part(x, 0, w) ^ part(x, 1, w) ^ part(x, 2, w);
+            case 2: return part(x, 0, w) ^ part(x, 1, w - 1) ^ part(x, 2, w - 2);
+            case 3: return part(x, 0, w) ^ part(x, 1, w) ^ part(x, 2, w) ^ part(x, 1, w - 1) ^ part(x, 2, w - 2);
+            default: return part(x, 2, w);
+        }
+    }
+
     // ab: [a (S) | b (S)] in LDS; returns the 2S-word product (inside scratch).
     __device__ __forceinline__ static u32 *run_ab(const u32 *ab, u32 *scratch) {
         u32 *R = scratch;

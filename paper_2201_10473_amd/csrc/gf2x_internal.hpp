@@ -9,7 +9,8 @@
 
 namespace gf2x {
 
-constexpr int kNumClasses = 21;
+constexpr int kNumDirect = 25;   // classes computed inside one workgroup
+constexpr int kNumClasses = 31;  // plus the staged classes
 constexpr uint32_t kKindCyclic = 0;
 constexpr uint32_t kKindFull = 1;
 constexpr uint32_t kMaxBits = 131072;
@@ -28,13 +29,19 @@ struct ClassInfo {
     int id;
     const char *name;
     int S;                   // padded operand size, 32-bit words
-    int lds_bytes;           // LDS of one workgroup
+    int lds_bytes;           // LDS of one workgroup (largest kernel of a staged class)
     long long base;          // 32x32 word products per multiplication
     long long ops;           // algorithmic VALU lane-ops per multiplication
+    int child;               // staged: class of the five point products; else -1
+    int direct;              // class computing the same size inside one workgroup
 };
 
 const ClassInfo &class_info(int cls);
 hipError_t prepare_kernels();
+// Staged classes need a device workspace: bytes for `count` products.
+size_t staged_workspace_bytes(int cls, uint32_t count);
+hipError_t launch_staged(int cls, const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
+                         const uint64_t *b_base, void *ws, int num_cu, hipStream_t s);
 hipError_t launch_single(int cls, const uint64_t *a, const uint64_t *b, uint64_t *c, uint32_t n, uint32_t kind,
                          hipStream_t s);
 hipError_t launch_batched(int cls, const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 
@@ -50,6 +51,39 @@ __global__ __launch_bounds__(NT) void k_mixed(const DevItem *items, u32 count, u
     }
 }
 
+// ----------------------------------------------------------- staged Toom-3
+// Point operands of every item: word w of operand x of point e of item i goes
+// to ws_in[((5 i + e) * 2 + x) * S1 + w].  The parent's words are read from
+// HBM (masked to n bits, zero beyond), split in three parts of m words.
+template <class Top>
+__global__ __launch_bounds__(256) void k_t3_eval(const DevItem *items, u32 count, const uint64_t *a_base,
+                                                 const uint64_t *b_base, u32 *ws_in) {
+    const size_t total = (size_t)count * 10 * Top::S1;
+    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
+         idx += (size_t)gridDim.x * blockDim.x)
+        ws_in[idx] = t3_eval_word<Top>(items, a_base, b_base, idx);
+}
+
+// Descriptors of the 5 * count point products: full products of S1-word
+// operands (n = 32 S1 bits), operands [a | b] at (5 i + e) * S1 uint64 words
+// of ws_in, results at (5 i + e) * S1 words of ws_out.
+__global__ void k_child_items(u32 count, u32 S1, u32 child_cls, DevItem *out) {
+    const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < 5 * count) {
+        const uint64_t base = (uint64_t)j * S1;
+        out[j] = DevItem{32u * S1, kKindFull, child_cls, 0u, base, base + S1 / 2, base};
+    }
+}
+
+// Interpolation of the five point products of each item, then the ring fold
+// or the full store (persistent workgroups).
+template <class Top>
+__global__ __launch_bounds__(NT) void k_t3_interp(const DevItem *items, u32 count, uint64_t *c_base,
+                                                  const u32 *ws_out) {
+    extern __shared__ u32 smem[];
+    for (u32 i = blockIdx.x; i < count; i += gridDim.x) t3_interp_item<Top>(items[i], c_base, ws_out + (size_t)i * 10 * Top::S1, smem);
+}
+
 // Device descriptors (public layout) -> internal layout; the class is taken
 // from the size table inside k_mixed.
 __global__ void k_convert_items(const gf2x_item *items, u32 count, DevItem *out) {
@@ -72,8 +106,25 @@ __global__ void k_fill_words(uint64_t *dst, size_t count, uint64_t seed) {
 
 // ------------------------------------------------------------ host side
 #define GF2X_INFO(id, name, T) \
-    {id, name, T::S, lds_words<T>() * 4, T::BASE, T::OPS},
-static const ClassInfo kClassInfo[] = {GF2X_CLASS_LIST(GF2X_INFO)};
+    {id, name, T::S, lds_words<T>() * 4, T::BASE, T::OPS, -1, id},
+#define GF2X_STAGED_INFO(id, name, T, c, C)                                                             \
+    {id, name, T::S, (lds_words<C>() > T::INTERP_SCRATCH ? lds_words<C>() : T::INTERP_SCRATCH) * 4, T::BASE, \
+     T::OPS, c, -2},
+static ClassInfo kClassInfo[] = {GF2X_CLASS_LIST(GF2X_INFO) GF2X_STAGED_LIST(GF2X_STAGED_INFO)};
+
+// the direct class of each staged class is the one with the same top schedule
+static int find_direct(int id) {
+    const ClassInfo &ci = kClassInfo[id];
+    if (ci.direct != -2) return ci.direct;
+    for (int c = 0; c < kNumDirect; ++c)
+        if (kClassInfo[c].S == ci.S && kClassInfo[c].ops == ci.ops) return c;
+    return -1;
+}
+static bool init_direct() {
+    for (int c = 0; c < kNumClasses; ++c) kClassInfo[c].direct = find_direct(c);
+    return true;
+}
+static const bool kDirectReady = init_direct();
 
 const ClassInfo &class_info(int cls) { return kClassInfo[cls]; }
 
@@ -89,8 +140,19 @@ static hipError_t set_lds_limit(const void *fn, int bytes) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
+#define GF2X_INTERP_PTR(id, name, T, c, C) reinterpret_cast<const void *>(&k_t3_interp<T>),
+static const void *kInterp[] = {GF2X_STAGED_LIST(GF2X_INTERP_PTR)};
+
 hipError_t prepare_kernels() {
-    for (int c = 0; c < kNumClasses; ++c) {
+    (void)kDirectReady;
+#define GF2X_INTERP_ATTR(id, name, T, c, C)                                                               \
+    {                                                                                                     \
+        hipError_t e = set_lds_limit(reinterpret_cast<const void *>(&k_t3_interp<T>), T::INTERP_SCRATCH * 4); \
+        if (e != hipSuccess) return e;                                                                    \
+    }
+    GF2X_STAGED_LIST(GF2X_INTERP_ATTR)
+    (void)kInterp;
+    for (int c = 0; c < kNumDirect; ++c) {
         hipError_t e = set_lds_limit(kSingle[c], kClassInfo[c].lds_bytes);
         if (e != hipSuccess) return e;
         e = set_lds_limit(kBatched[c], kClassInfo[c].lds_bytes);
@@ -130,6 +192,53 @@ hipError_t launch_batched(int cls, const DevItem *items, uint32_t count, uint64_
     BatchedFn fn = reinterpret_cast<BatchedFn>(const_cast<void *>(fnp));
     hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), lds, s, items, count, c_base, a_base, b_base);
     return hipGetLastError();
+}
+
+size_t staged_workspace_bytes(int cls, uint32_t count) {
+    const ClassInfo &ci = kClassInfo[cls];
+    if (ci.child < 0) return 0;
+    const size_t S1 = (size_t)kClassInfo[ci.child].S;
+    const size_t in = (size_t)count * 10 * S1 * 4, items = (size_t)count * 5 * sizeof(DevItem);
+    return 2 * ((in + 255) / 256 * 256) + items;
+}
+
+template <class T, int CHILD>
+static hipError_t staged_impl(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
+                              const uint64_t *b_base, void *ws, int num_cu, hipStream_t s) {
+    constexpr int S1 = T::S1;
+    const size_t in_bytes = ((size_t)count * 10 * S1 * 4 + 255) / 256 * 256;
+    u32 *ws_in = reinterpret_cast<u32 *>(ws);
+    u32 *ws_out = reinterpret_cast<u32 *>(reinterpret_cast<char *>(ws) + in_bytes);
+    DevItem *child = reinterpret_cast<DevItem *>(reinterpret_cast<char *>(ws) + 2 * in_bytes);
+    const size_t total = (size_t)count * 10 * S1;
+    const uint32_t eval_grid = (uint32_t)std::min<size_t>((total + 255) / 256, (size_t)num_cu * 16);
+    hipLaunchKernelGGL(k_t3_eval<T>, dim3(eval_grid), dim3(256), 0, s, items, count, a_base, b_base, ws_in);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_child_items, dim3((5 * count + 255) / 256), dim3(256), 0, s, count, (u32)S1, (u32)CHILD,
+                       child);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_batched(CHILD, child, 5 * count, reinterpret_cast<uint64_t *>(ws_out),
+                       reinterpret_cast<const uint64_t *>(ws_in), reinterpret_cast<const uint64_t *>(ws_in), num_cu,
+                       s);
+    if (e != hipSuccess) return e;
+    const void *fn = reinterpret_cast<const void *>(&k_t3_interp<T>);
+    const int lds = T::INTERP_SCRATCH * 4;
+    const long long cap = (long long)num_cu * occupancy(fn, lds);
+    const uint32_t grid = (uint32_t)(count < cap ? count : cap);
+    hipLaunchKernelGGL(k_t3_interp<T>, dim3(grid), dim3(NT), lds, s, items, count, c_base, ws_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_staged(int cls, const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
+                         const uint64_t *b_base, void *ws, int num_cu, hipStream_t s) {
+    switch (cls) {
+#define GF2X_STAGED_CASE(id, name, T, c, C) \
+    case id: return staged_impl<T, c>(items, count, c_base, a_base, b_base, ws, num_cu, s);
+        GF2X_STAGED_LIST(GF2X_STAGED_CASE)
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_fill_words(uint64_t *dst, size_t count, uint64_t seed, hipStream_t s) {

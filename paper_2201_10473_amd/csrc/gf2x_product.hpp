@@ -44,6 +44,10 @@ using Class17 = SeqT3<SeqT3<ParK2<5, 7>>>;
 using Class18 = SeqT3<SeqT3<ParK2<5, 10>>>;
 using Class19 = SeqT3<SeqT3<SeqT3<ParK2<5, 4>>>>;
 using Class20 = SeqT3<SeqT3<SeqT3<ParK2<5, 5>>>>;
+using Class21 = SeqT3<ParK2<5, 7>>;
+using Class22 = SeqT3<ParK2<5, 4>>;
+using Class23 = ParK2<5, 6>;
+using Class24 = ParK2<5, 9>;
 
 // X(id, name, schedule type)
 #define GF2X_CLASS_LIST(X) \
@@ -67,11 +71,30 @@ using Class20 = SeqT3<SeqT3<SeqT3<ParK2<5, 5>>>>;
     X(17, "T3.T3.K2^5.U7", Class17) \
     X(18, "T3.T3.K2^5.U10", Class18) \
     X(19, "T3.T3.T3.K2^5.U4", Class19) \
-    X(20, "T3.T3.T3.K2^5.U5", Class20)
+    X(20, "T3.T3.T3.K2^5.U5", Class20) \
+    X(21, "T3.K2^5.U7", Class21) \
+    X(22, "T3.K2^5.U4", Class22) \
+    X(23, "K2^5.U6", Class23) \
+    X(24, "K2^5.U9", Class24)
+
+// Staged classes: the top Toom-3 level of a class is spread over workgroups.
+// An evaluation kernel writes the five point operands of every product to a
+// workspace, the child class computes all of them as one batch of full
+// products, and an interpolation kernel recombines and folds.
+// X(id, name, top schedule type, child class id, child schedule type)
+#define GF2X_STAGED_LIST(X) \
+    X(25, "G.T3.T3.K2^5.U4", Class14, 22, Class22) \
+    X(26, "G.T3.T3.K2^5.U5", Class15, 9, Class9) \
+    X(27, "G.T3.T3.K2^5.U7", Class17, 21, Class21) \
+    X(28, "G.T3.K2^5.U6", Class10, 23, Class23) \
+    X(29, "G.T3.K2^5.U9", Class13, 24, Class24) \
+    X(30, "G.T3.T3.T3.K2^5.U5", Class20, 15, Class15)
 
 #define GF2X_COUNT_CLASS(id, name, T) +1
 constexpr int NUM_CLASSES = 0 GF2X_CLASS_LIST(GF2X_COUNT_CLASS);
-static_assert(NUM_CLASSES == kNumClasses, "class count mismatch");
+#define GF2X_COUNT_STAGED(id, name, T, c, C) +1
+constexpr int NUM_STAGED = 0 GF2X_STAGED_LIST(GF2X_COUNT_STAGED);
+static_assert(NUM_CLASSES == kNumDirect && NUM_CLASSES + NUM_STAGED == kNumClasses, "class count mismatch");
 
 template <class Sch>
 constexpr int lds_words() { return 2 * Sch::S + Sch::SCRATCH; }
@@ -138,6 +161,43 @@ __device__ __forceinline__ void store_full(const u32 *R, u32 n, uint64_t *c) {
     const int out32 = 4 * (int)((n + 63u) / 64u);
     u32 *c32 = reinterpret_cast<u32 *>(c);
     for (int k = threadIdx.x; k < out32; k += NT) c32[k] = k < 2 * S ? R[k] : 0u;
+}
+
+// Staged Toom-3, evaluation: word idx of the point operands of a batch
+// (layout ((5 i + e) * 2 + x) * S1 + w) from the items' operands in HBM,
+// masked to n bits, zero beyond, split in three parts of m words.
+template <class Top>
+__device__ __forceinline__ u32 t3_eval_word(const DevItem *items, const uint64_t *a_base, const uint64_t *b_base,
+                                            size_t idx) {
+    constexpr int S1 = Top::S1, m = Top::m;
+    const u32 i = (u32)(idx / (10 * S1));
+    const int r = (int)(idx - (size_t)i * 10 * S1);
+    const int e = r / (2 * S1);
+    const int x = (r - e * 2 * S1) / S1;
+    const int w = r - e * 2 * S1 - x * S1;
+    const DevItem it = items[i];
+    const u32 *src = reinterpret_cast<const u32 *>(x ? b_base + it.b_off : a_base + it.a_off);
+    const int w32 = (int)((it.n + 31u) / 32u);
+    const u32 s = it.n % 32u;
+    const u32 top = s ? ((1u << s) - 1u) : 0xFFFFFFFFu;
+    auto part = [&](int, int p, int j) -> u32 {
+        if (j < 0 || j >= m) return 0u;
+        const int k = p * m + j;
+        if (k >= w32) return 0u;
+        const u32 v = src[k];
+        return k == w32 - 1 ? (v & top) : v;
+    };
+    return Top::point_word(e, x, w, part);
+}
+
+// Staged Toom-3, interpolation of one item from its five point products
+// (2*S1 words each, consecutive), then the ring fold or the full store.
+template <class Top>
+__device__ __forceinline__ void t3_interp_item(const DevItem &it, uint64_t *c_base, const u32 *products, u32 *smem) {
+    const u32 *R = Top::interp_from(products, smem);
+    if (it.kind == kKindCyclic) store_cyclic<Top::S>(R, it.n, c_base + it.c_off);
+    else store_full<Top::S>(R, it.n, c_base + it.c_off);
+    __syncthreads();
 }
 
 template <class Sch>

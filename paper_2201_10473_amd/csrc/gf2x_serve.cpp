@@ -180,7 +180,7 @@ bool launch(gf2x_srv *srv) {
     for (uint32_t i = 0; i < count; ++i) {
         const Request &r = sl->reqs[i];
         const uint64_t W = (r.n + 63u) / 64u;
-        const int cls = srv->ctx->cls_of_w32[(r.n + 31u) / 32u];
+        const int cls = class_info(srv->ctx->cls_of_w32[(r.n + 31u) / 32u]).direct;
         tmp[i] = DevItem{r.n, kKindCyclic, (uint32_t)cls, 0u, off, off, off};
         sl->c_off[i] = off;
         off += W;

@@ -165,3 +165,69 @@ extern "C" int emu_toeplitz(const uint64_t *h, uint32_t n, const uint64_t *R, ui
         }
     return 0;
 }
+
+// Staged class `id` (from the staged list) on one product: evaluation for
+// every point word, the five point products by the child class (emulated
+// workgroups, full products), then the interpolation workgroup.
+namespace {
+struct InterpJob {
+    int which;
+    gf2x::DevItem it;
+    uint64_t *c;
+    const uint32_t *products;
+    uint32_t *smem;
+    unsigned tid;
+};
+void *interp_worker(void *p) {
+    InterpJob *j = static_cast<InterpJob *>(p);
+    threadIdx.x = j->tid;
+    int k = 0;
+#define EMU_INTERP(id, name, T, cid, C) \
+    if (k++ == j->which) gf2x::t3_interp_item<gf2x::T>(j->it, j->c, j->products, j->smem);
+    GF2X_STAGED_LIST(EMU_INTERP)
+    return nullptr;
+}
+}  // namespace
+
+extern "C" int emu_staged(int which, const uint64_t *a, const uint64_t *b, uint64_t *c, uint32_t n, uint32_t kind) {
+    int k = 0, S1 = 0, m = 0, child = -1, interp_words = 0;
+#define EMU_STAGED_INFO(id, name, T, cc, C) \
+    if (k++ == which) { S1 = gf2x::T::S1; m = gf2x::T::m; child = cc; interp_words = gf2x::T::INTERP_SCRATCH; }
+    GF2X_STAGED_LIST(EMU_STAGED_INFO)
+    if (child < 0) return -1;
+    (void)m;
+    gf2x::DevItem it{n, kind, 0u, 0u, 0, 0, 0};
+    std::vector<uint32_t> ws_in(10 * (size_t)S1), ws_out(10 * (size_t)S1);
+    k = 0;
+    for (size_t idx = 0; idx < ws_in.size(); ++idx) {
+        int kk = 0;
+#define EMU_EVAL(id, name, T, cc, C) \
+        if (kk++ == which) ws_in[idx] = gf2x::t3_eval_word<gf2x::T>(&it, a, b, idx);
+        GF2X_STAGED_LIST(EMU_EVAL)
+    }
+    for (int e = 0; e < 5; ++e) {
+        const uint64_t *pa = reinterpret_cast<const uint64_t *>(ws_in.data() + (size_t)e * 2 * S1);
+        const uint64_t *pb = pa + S1 / 2;
+        uint64_t *pc = reinterpret_cast<uint64_t *>(ws_out.data() + (size_t)e * 2 * S1);
+        emu_mul(child, pa, pb, pc, 32u * S1, 1u);
+    }
+    std::vector<uint32_t> smem(interp_words);
+    pthread_barrier_init(&g_bar, nullptr, gf2x::NT);
+    std::vector<pthread_t> th(gf2x::NT);
+    std::vector<InterpJob> jobs(gf2x::NT);
+    for (int t = 0; t < gf2x::NT; ++t) {
+        jobs[t] = InterpJob{which, it, c, ws_out.data(), smem.data(), (unsigned)t};
+        pthread_create(&th[t], nullptr, interp_worker, &jobs[t]);
+    }
+    for (int t = 0; t < gf2x::NT; ++t) pthread_join(th[t], nullptr);
+    pthread_barrier_destroy(&g_bar);
+    return 0;
+}
+
+extern "C" int emu_staged_words(int which) {
+    int k = 0, S = 0;
+#define EMU_STAGED_S(id, name, T, cc, C) \
+    if (k++ == which) S = gf2x::T::S;
+    GF2X_STAGED_LIST(EMU_STAGED_S)
+    return S;
+}

@@ -33,6 +33,8 @@ def emu(tmp_path_factory):
     lib.emu_mul.argtypes = [ctypes.c_int, u64p, u64p, u64p, ctypes.c_uint32, ctypes.c_uint32]
     lib.emu_class_words.argtypes = [ctypes.c_int]
     lib.emu_toeplitz.argtypes = [u64p, ctypes.c_uint32, u64p, u64p, ctypes.c_uint32]
+    lib.emu_staged.argtypes = [ctypes.c_int, u64p, u64p, u64p, ctypes.c_uint32, ctypes.c_uint32]
+    lib.emu_staged_words.argtypes = [ctypes.c_int]
     return lib
 
 
@@ -51,7 +53,7 @@ def _run(lib, cls, n, seed):
 
 # classes 19 and 20 (three Toom-3 levels) take ~15 s each on the CPU and are
 # covered on the GPU by test_every_schedule_class
-@pytest.mark.parametrize("cls", range(19))
+@pytest.mark.parametrize("cls", list(range(19)) + [21, 22, 23, 24])
 def test_class_full_and_ragged(emu, cls):
     S = emu.emu_class_words(cls)
     for n in sorted({S * 32, max(1, S * 32 - 37)}):
@@ -72,3 +74,23 @@ def test_toeplitz_tile(emu, n, count):
     R[:, -1] &= inputs.top_mask(n)
     for i in range(count):
         assert np.array_equal(C[i], oracle.mul_cyclic(h, R[i], n)), i
+
+
+@pytest.mark.parametrize("which", [0, 3, 4])
+def test_staged_toom3(emu, which):
+    """Top Toom-3 level spread over workgroups: evaluation words, the five
+    point products by the child class, interpolation and fold."""
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    S = emu.emu_staged_words(which)
+    for n in (S * 32, S * 32 - 37):
+        a = inputs.dense(n, 21, which, 0)
+        b = inputs.dense(n, 21, which, 1)
+        a[-1] |= ~inputs.top_mask(n)
+        W = oracle.words(n)
+        c = np.zeros(W, dtype=np.uint64)
+        f = np.zeros(2 * W, dtype=np.uint64)
+        emu.emu_staged(which, a.ctypes.data_as(u64p), b.ctypes.data_as(u64p), c.ctypes.data_as(u64p), n, 0)
+        emu.emu_staged(which, a.ctypes.data_as(u64p), b.ctypes.data_as(u64p), f.ctypes.data_as(u64p), n, 1)
+        a[-1] &= inputs.top_mask(n)
+        assert np.array_equal(c, oracle.mul_cyclic(a, b, n))
+        assert np.array_equal(f, oracle.mul(a, b, n))

@@ -109,6 +109,9 @@ ALL_CLASSES = [
     ("T3.K2^4.U12", 570), ("T3.T3.K2^5.U3", 840), ("T3.K2^5.U9", 858), ("T3.T3.K2^5.U4", 1128),
     ("T3.T3.K2^5.U5", 1416), ("T3.T3.K2^4.U13", 1848), ("T3.T3.K2^5.U7", 1992), ("T3.T3.K2^5.U10", 2856),
     ("T3.T3.T3.K2^5.U4", 3378), ("T3.T3.T3.K2^5.U5", 4242),
+    ("T3.K2^5.U7", 666), ("T3.K2^5.U4", 378), ("K2^5.U6", 192), ("K2^5.U9", 288),
+    ("G.T3.T3.K2^5.U4", 1128), ("G.T3.T3.K2^5.U5", 1416), ("G.T3.T3.K2^5.U7", 1992), ("G.T3.K2^5.U6", 570),
+    ("G.T3.K2^5.U9", 858), ("G.T3.T3.T3.K2^5.U5", 4242),
 ]
 
 
@@ -127,6 +130,12 @@ def test_every_schedule_class(tmp_path, name, S):
             b = inputs.dense(n, SEED + 5, S, 1)
             assert np.array_equal(_single(c, n, a, b, gf2x.KIND_CYCLIC), oracle.mul_cyclic(a, b, n))
             assert np.array_equal(_single(c, n, a, b, gf2x.KIND_FULL), oracle.mul(a, b, n))
+            # a small batch, where staged classes take their staged path
+            for kind in (gf2x.KIND_CYCLIC, gf2x.KIND_FULL):
+                A, B, (C,) = _batched(c, n, 5, SEED + 5, kind=kind)
+                for i in range(5):
+                    ref = oracle.mul_cyclic(A[i], B[i], n) if kind == gf2x.KIND_CYCLIC else oracle.mul(A[i], B[i], n)
+                    assert np.array_equal(C[i], ref), (name, n, kind, i)
 
 
 def _batched(ctx, n, count, seed, kind=gf2x.KIND_CYCLIC, flags=0, reps=1):
