@@ -176,6 +176,42 @@ def time_mixed(ctx, steps, seed, count=8192):
             "valu_frac": round(ops / (ms * 1e-3) / VALU_PEAK, 4)}
 
 
+def single_latency(ctx, n, calls, warmup, seed):
+    """One product per call, each call synchronized: median device time (HIP
+    events) and median host round trip, after `warmup` untimed calls."""
+    import numpy as np
+    import torch
+
+    from paper_2201_10473_amd import gf2x, inputs
+
+    W = gf2x.words(n)
+    a = inputs.dense(n, seed, 0, 0)
+    b = inputs.dense(n, seed, 0, 1)
+    dA = torch.from_numpy(a.view(np.int64)).cuda()
+    dB = torch.from_numpy(b.view(np.int64)).cuda()
+    dC = torch.zeros(W, dtype=torch.int64, device="cuda")
+    for _ in range(warmup):
+        ctx.mul_cyclic(dC, dA, dB, n)
+    torch.cuda.synchronize()
+    dev, host = [], []
+    for _ in range(calls):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        s.record()
+        ctx.mul_cyclic(dC, dA, dB, n)
+        e.record()
+        e.synchronize()
+        host.append(time.perf_counter() - t0)
+        dev.append(s.elapsed_time(e))
+    import oracle
+
+    if not np.array_equal(dC.cpu().numpy().view(np.uint64), oracle.mul_cyclic(a, b, n)):
+        raise AssertionError("single product at n=%d differs from the oracle" % n)
+    return {"n": n, "calls": calls, "median_device_us": round(1e3 * float(np.median(dev)), 2),
+            "median_host_us": round(1e6 * float(np.median(host)), 2),
+            "schedule": ctx.schedule_info(n)[3]}
+
+
 def check_sample(res, n, count, k=6):
     """Spot-check k items against the oracle and all items against parity."""
     import numpy as np
@@ -341,7 +377,11 @@ def main():
 
     mixed = None
     serving = []
+    single = None
     if not args.only_n:
+        log("single product latency n=12323 (1000 calls after 100 warm-ups)")
+        single = single_latency(ctx, 12323, 1000, 100, inputs.SEED_BASE + 1)
+        log("  %s" % single)
         log("mixed workload: 8192 products, six sizes, half dense x sparse")
         mixed = time_mixed(ctx, 10, inputs.SEED_BASE + 4)
         log("  %s" % mixed)
@@ -393,6 +433,7 @@ def main():
             {str(n): {k: (round(v, 4) if isinstance(v, float) else v) for k, v in r.items()}
              for n, r in results.items()},
             shared_operand=shared,
+            single_product=single,
             mixed=mixed,
             serving=serving,
         ),
