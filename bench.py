@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "products/sec at n=17669 & 57637 (batched vs one-per-launch); % int-op roofline"
-VALU_PEAK = 256 * 64 * 2.4e9  # int32 lane-ops per second
+VALU_PEAK = 256 * 4 * 32 * 2.4e9  # int32 lane-ops per second: 256 CU x 4 SIMD x 32 lanes per clock
 INT8_PEAK = 5.0e15  # dense int8 matrix ops per second (2 per multiply-add)
 BATCH = 4096
 
