@@ -21,7 +21,18 @@ ARCH = "gfx950"
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 
-SOURCES = ["gf2x_kernels.hip", "gf2x_toeplitz.hip", "gf2x_api.cpp", "gf2x_serve.cpp"]
+# the heaviest translation units first, so that they start first
+SOURCES = [
+    "gf2x_kern_staged.hip",
+    "gf2x_kern_d0.hip",
+    "gf2x_kern_d1.hip",
+    "gf2x_kern_d2.hip",
+    "gf2x_kern_d3.hip",
+    "gf2x_kernels.hip",
+    "gf2x_toeplitz.hip",
+    "gf2x_api.cpp",
+    "gf2x_serve.cpp",
+]
 
 
 def _compile(src):
@@ -40,7 +51,8 @@ def _compile(src):
 
 def build_library(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp] + objs

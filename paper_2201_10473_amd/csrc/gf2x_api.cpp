@@ -358,8 +358,7 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
         if (rc) return rc;
         if (ctx->ws_used) HIP_TRY(hipStreamWaitEvent(s, ctx->ws_free, 0));
         HIP_TRY(launch_convert_items(items, count, ctx->d_items, s));
-        HIP_TRY(launch_mixed(ctx->d_items, count, c_base, a_base, b_base, ctx->d_cls, true, 160 * 1024,
-                             ctx->num_cu, s));
+        HIP_TRY(launch_mixed(ctx->d_items, count, c_base, a_base, b_base, ctx->d_cls, ctx->num_cu, s));
         HIP_TRY(hipEventRecord(ctx->ws_free, s));
         ctx->ws_used = true;
         return GF2X_OK;

@@ -32,6 +32,21 @@ typedef uint32_t u32;
 constexpr int NT = 256;      // threads per workgroup
 constexpr int NWAVE = NT / 64;
 
+// The thread index, re-read at each use: index arithmetic derived from it is
+// then recomputed in each pass instead of being hoisted out of the item and
+// point loops and kept live (and spilled) across the whole product.  Host-side
+// builds of these headers use the plain index.
+__device__ __forceinline__ int tid() {
+#if defined(__HIP_DEVICE_COMPILE__)
+    int t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+    __builtin_assume(t >= 0 && t < NT);
+    return t;
+#else
+    return (int)threadIdx.x;
+#endif
+}
+
 constexpr long long pow3(int d) { return d == 0 ? 1 : 3 * pow3(d - 1); }
 
 // acc ^ (x & m) in one gfx950 v_bitop3_b32 (truth table 0x78 over
@@ -60,12 +75,12 @@ __device__ __forceinline__ void par_map(u32 *dst, F f) {
     u32 v[IT];
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
-        const int idx = threadIdx.x + i * NT;
+        const int idx = tid() + i * NT;
         if (IT * NT == TOTAL || idx < TOTAL) v[i] = f(idx);
     }
 #pragma unroll
     for (int i = 0; i < IT; ++i) {
-        const int idx = threadIdx.x + i * NT;
+        const int idx = tid() + i * NT;
         if (IT * NT == TOTAL || idx < TOTAL) dst[idx] = v[i];
     }
 }
@@ -130,61 +145,128 @@ struct LdsSource {
 };
 
 // ----------------------------------------------------- 2-way Karatsuba levels
+// f(row, col) for 0 <= row < ROWS and 0 <= col < COLS, spread over the
+// workgroup.  A thread keeps one column and steps through the rows, so the
+// per-element index arithmetic of a level pass reduces to constant offsets
+// from one address, and the condition on the column is fixed per thread.
+template <int ROWS, int COLS, class F>
+__device__ __forceinline__ void grid_map(F f) {
+    if constexpr (COLS <= NT) {
+        constexpr int RPP = NT / COLS;  // rows per pass
+        constexpr int PASSES = (ROWS + RPP - 1) / RPP;
+        const int t = tid();
+        const int row0 = t / COLS;
+        const int col = t - row0 * COLS;
+        if (row0 < RPP) {
+#pragma unroll
+            for (int q = 0; q < PASSES; ++q) {
+                const int row = row0 + q * RPP;
+                if ((ROWS % RPP) == 0 || row < ROWS) f(row, col);
+            }
+        }
+    } else {
+#pragma unroll 1
+        for (int row = 0; row < ROWS; ++row)
+            for (int col = tid(); col < COLS; col += NT) f(row, col);
+    }
+}
+
+// As grid_map, in two phases: load(row, col, v) for every element of the
+// thread, then store(row, col, v) for every element, so that a pass over a
+// level costs one LDS round trip instead of one per row.  load must not read
+// what store writes.
+template <int ROWS, int COLS, int NV, class L, class S>
+__device__ __forceinline__ void grid_map2(L load, S store) {
+    if constexpr (COLS <= NT) {
+        constexpr int RPP = NT / COLS;
+        constexpr int PASSES = (ROWS + RPP - 1) / RPP;
+        const int t = tid();
+        const int row0 = t / COLS;
+        const int col = t - row0 * COLS;
+        if (row0 < RPP) {
+            u32 v[PASSES][NV];
+#pragma unroll
+            for (int q = 0; q < PASSES; ++q) {
+                const int row = row0 + q * RPP;
+                if ((ROWS % RPP) == 0 || row < ROWS) load(row, col, v[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < PASSES; ++q) {
+                const int row = row0 + q * RPP;
+                if ((ROWS % RPP) == 0 || row < ROWS) store(row, col, v[q]);
+            }
+        }
+    } else {
+#pragma unroll 1
+        for (int row = 0; row < ROWS; ++row)
+            for (int col = tid(); col < COLS; col += NT) {
+                u32 v[NV];
+                load(row, col, v);
+                store(row, col, v);
+            }
+    }
+}
+
+// 3-input XOR in one v_bitop3_b32 (truth table 0x96).
+__device__ __forceinline__ u32 xor3(u32 a, u32 b, u32 c) { return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96); }
+
 // Splitting (KaratRec, Appendix A): a node of SL words with operands [a | b]
 // becomes three children of H = SL/2 words, in this order:
 //   child 0: (a0, b0), child 1: (a1, b1), child 2: (a0 + a1, b0 + b1).
-// Every level is stored densely: node v's operands at v*2*SL.
+// Every level is stored densely: node v's operands at v*2*SL.  Column
+// r = x*H + w of node v is word w of operand x of each child.
 template <int NL, int SL>
 __device__ __forceinline__ void k2_split(const u32 *src, u32 *dst) {
     constexpr int H = SL / 2;
-    constexpr int TOTAL = NL * 2 * H;
-    for (int idx = threadIdx.x; idx < TOTAL; idx += NT) {
-        const int v = idx / (2 * H);
-        const int r = idx - v * 2 * H;  // r = x*H + w, x = which operand
-        const int x = r / H;
-        const int w = r - x * H;
-        const u32 lo = src[v * 2 * SL + x * SL + w];
-        const u32 hi = src[v * 2 * SL + x * SL + H + w];
-        u32 *d = dst + 3 * v * 2 * H + r;
-        d[0] = lo;
-        d[2 * H] = hi;
-        d[4 * H] = lo ^ hi;
-    }
+    grid_map2<NL, 2 * H, 2>(
+        [&](int v, int r, u32 (&x)[2]) {
+            const u32 *s = src + v * 2 * SL + r + (r >= H ? H : 0);  // word w of operand x: x*SL + w
+            x[0] = s[0];
+            x[1] = s[H];
+        },
+        [&](int v, int r, const u32 (&x)[2]) {
+            u32 *d = dst + 3 * v * 2 * H + r;
+            d[0] = x[0];
+            d[2 * H] = x[1];
+            d[4 * H] = x[0] ^ x[1];
+        });
 }
 
 // The root split, reading the root operands from a source.
 template <int SL, class Src>
 __device__ __forceinline__ void k2_split_src(const Src &src, u32 *dst) {
     constexpr int H = SL / 2;
-    for (int idx = threadIdx.x; idx < 2 * H; idx += NT) {
-        const int x = idx / H;
-        const int w = idx - x * H;
+    grid_map<1, 2 * H>([&](int, int r) {
+        const int x = r >= H ? 1 : 0;
+        const int w = r - x * H;
         const u32 lo = src.get(x, w);
         const u32 hi = src.get(x, H + w);
-        dst[idx] = lo;
-        dst[2 * H + idx] = hi;
-        dst[4 * H + idx] = lo ^ hi;
-    }
+        dst[r] = lo;
+        dst[2 * H + r] = hi;
+        dst[4 * H + r] = lo ^ hi;
+    });
 }
 
 // Reconstruction (KaratRec): R = R0 + (R0 + R1 + R2) X^{32H} + R1 X^{64H}
 // with children products R_k of 2H words stored densely; since R0 and R1 are
 // adjacent, [R0 | R1] already is R0 + R1 X^{64H}.  Parent products are 4H
-// words, stored densely.
+// words, stored densely.  Column j < 2H of node v writes the middle word
+// H + j and one outer word: word j (= R0[j]) when j < H, else word 2H + j
+// (= R1[j]).
 template <int NL, int H>
 __device__ __forceinline__ void k2_merge(const u32 *src, u32 *dst) {
-    constexpr int TOTAL = NL * 4 * H;
-    for (int idx = threadIdx.x; idx < TOTAL; idx += NT) {
-        const int v = idx / (4 * H);
-        const int k = idx - v * 4 * H;
-        const u32 *R = src + 3 * v * 2 * H;
-        u32 val = R[k];
-        if (k >= H && k < 3 * H) {
-            const int j = k - H;
-            val ^= R[j] ^ R[j + 2 * H] ^ R[j + 4 * H];
-        }
-        dst[idx] = val;
-    }
+    grid_map2<NL, 2 * H, 2>(
+        [&](int v, int j, u32 (&x)[2]) {
+            const u32 *R = src + 3 * v * 2 * H + j;
+            const u32 r0 = R[0], r1 = R[2 * H];
+            x[0] = xor3(R[H], r0, r1) ^ R[4 * H];
+            x[1] = j < H ? r0 : r1;
+        },
+        [&](int v, int j, const u32 (&x)[2]) {
+            u32 *O = dst + v * 4 * H;
+            O[H + j] = x[0];
+            O[j < H ? j : 2 * H + j] = x[1];
+        });
 }
 
 // D levels of 2-way Karatsuba over T-word units, breadth first, 3^D <= NT
@@ -249,7 +331,7 @@ struct ParK2 {
     // product into the parent (last merge).  Source Src is only used for D == 1.
     template <class Src>
     __device__ __forceinline__ static void units(const Src &src, u32 *DA) {
-        const int u = threadIdx.x;
+        const int u = tid();
         const bool active = u < (int)UNITS;
         const int v = u / 3, k = u - 3 * (u / 3);
         u32 a[T], b[T], c[2 * T];
@@ -274,7 +356,7 @@ struct ParK2 {
             }
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < DA_WORDS; i += NT) DA[i] = 0;
+        for (int i = tid(); i < DA_WORDS; i += NT) DA[i] = 0;
         __syncthreads();
         if (active) {
             unit_mul<T>(a, b, c);
@@ -296,7 +378,7 @@ struct ParK2 {
         u32 *DB = scratch + DA_WORDS;
         if constexpr (D == 0) {
             u32 a[T], b[T], c[2 * T];
-            if (threadIdx.x == 0) {
+            if (tid() == 0) {
 #pragma unroll
                 for (int w = 0; w < T; ++w) {
                     a[w] = src.get(0, w);
@@ -330,7 +412,7 @@ struct ParK2 {
 template <int L>
 __device__ __forceinline__ void div_xx1_pair(u32 *x, u32 *y, u32 *tmp) {
     constexpr int C = (L + NT - 1) / NT;
-    const int t = threadIdx.x;
+    const int t = tid();
     u32 vx[C], vy[C];
     u32 ax = 0, ay = 0;
 #pragma unroll
@@ -432,30 +514,62 @@ struct SeqT3 {
     static constexpr long long OPS = 5 * Child::OPS + 46LL * S1 + 12LL * m;
 
     // Fold point product p (2*S1 words) into R and the numerators Sa, Ua.
+    // Only the words of R that receive a nonzero term are visited, and every
+    // new value is computed before any is stored (one LDS round trip).
     template <int E>
     __device__ __forceinline__ static void absorb(const u32 *p, u32 *R, u32 *Sa, u32 *Ua) {
         auto P = [&](int j) -> u32 { return (j >= 0 && j < 2 * S1) ? p[j] : 0u; };
-        if constexpr (E == 0 || E == 1 || E == 4) {
-            for (int r = threadIdx.x; r < R_WORDS; r += NT) {
+        // R gets P(r) + P(r-m) (point 0), P(r-m) (point 1), P(r-m) + P(r-4m) (point inf)
+        constexpr int R_LO = (E == 0 || E == 2 || E == 3) ? 0 : m;
+        constexpr int R_HI = (E == 0) ? m + 2 * S1 : (E == 1) ? m + 2 * S1 : (E == 4) ? R_WORDS : 0;
+        constexpr int NR = R_HI - R_LO, IR = (NR + NT - 1) / NT;
+        constexpr int NS = (E != 4) ? 2 * S1 : 0, IS = (NS + NT - 1) / NT;
+        constexpr int NU = (E != 0) ? UA_WORDS : 0, IU = (NU + NT - 1) / NT;
+        static_assert(R_HI <= R_WORDS, "point 0 and 1 terms fit in R");
+        const int t = tid();
+        u32 vr[IR > 0 ? IR : 1], vs[IS > 0 ? IS : 1], vu[IU > 0 ? IU : 1];
+#pragma unroll
+        for (int i = 0; i < IR; ++i) {
+            const int r = R_LO + t + i * NT;
+            if (r < R_HI) {
                 u32 v;
                 if constexpr (E == 0) v = P(r) ^ P(r - m);
                 else if constexpr (E == 1) v = P(r - m);
                 else v = P(r - m) ^ P(r - 4 * m);
-                R[r] ^= v;
+                vr[i] = R[r] ^ v;
             }
         }
-        if constexpr (E != 4) {
-            for (int k = threadIdx.x; k < 2 * S1; k += NT) Sa[k] ^= p[k];
+#pragma unroll
+        for (int i = 0; i < IS; ++i) {
+            const int k = t + i * NT;
+            if (k < NS) vs[i] = Sa[k] ^ p[k];
         }
-        if constexpr (E != 0) {
-            for (int k = threadIdx.x; k < UA_WORDS; k += NT) {
+#pragma unroll
+        for (int i = 0; i < IU; ++i) {
+            const int k = t + i * NT;
+            if (k < NU) {
                 u32 v;
                 if constexpr (E == 1) v = P(k);
                 else if constexpr (E == 2) v = P(k - 1);
                 else if constexpr (E == 3) v = P(k) ^ P(k - 1);
                 else v = P(k - 1) ^ P(k - 4);
-                Ua[k] ^= v;
+                vu[i] = Ua[k] ^ v;
             }
+        }
+#pragma unroll
+        for (int i = 0; i < IR; ++i) {
+            const int r = R_LO + t + i * NT;
+            if (r < R_HI) R[r] = vr[i];
+        }
+#pragma unroll
+        for (int i = 0; i < IS; ++i) {
+            const int k = t + i * NT;
+            if (k < NS) Sa[k] = vs[i];
+        }
+#pragma unroll
+        for (int i = 0; i < IU; ++i) {
+            const int k = t + i * NT;
+            if (k < NU) Ua[k] = vu[i];
         }
     }
 
@@ -487,7 +601,7 @@ struct SeqT3 {
         u32 *Sa = R + R_WORDS;
         u32 *Ua = Sa + SA_WORDS;
         u32 *tmp = Ua + UA_WORDS;
-        for (int k = threadIdx.x; k < R_WORDS + SA_WORDS + UA_WORDS; k += NT) R[k] = 0;
+        for (int k = tid(); k < R_WORDS + SA_WORDS + UA_WORDS; k += NT) R[k] = 0;
         __syncthreads();
         absorb<0>(products + 0 * 2 * S1, R, Sa, Ua);
         __syncthreads();
@@ -527,7 +641,7 @@ struct SeqT3 {
         u32 *cin = Ua + UA_WORDS;
         u32 *tmp = cin + CIN_WORDS;
         u32 *cs = tmp + TMP_WORDS;
-        for (int k = threadIdx.x; k < R_WORDS + SA_WORDS + UA_WORDS; k += NT) R[k] = 0;
+        for (int k = tid(); k < R_WORDS + SA_WORDS + UA_WORDS; k += NT) R[k] = 0;
         // (the barriers inside the first child run order these stores before any absorb)
         point<0>(ab, R, Sa, Ua, cin, cs);
         point<1>(ab, R, Sa, Ua, cin, cs);

@@ -1,5 +1,6 @@
 // gf2x_internal.hpp -- interface between the C ABI layer (gf2x_api.cpp) and
-// the kernel translation unit (gf2x_kernels.hip).  Not part of the public ABI.
+// the kernel translation units (gf2x_kernels.hip, gf2x_kern_*.hip).  Not part
+// of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -48,8 +49,8 @@ hipError_t launch_batched(int cls, const DevItem *items, uint32_t count, uint64_
                           const uint64_t *b_base, int num_cu, hipStream_t s);
 hipError_t launch_fill_words(uint64_t *dst, size_t count, uint64_t seed, hipStream_t s);
 hipError_t launch_convert_items(const struct gf2x_item *items, uint32_t count, DevItem *out, hipStream_t s);
+// Items whose classes come from the device table cls_of_w32 (direct classes).
 hipError_t launch_mixed(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
-                        const uint64_t *b_base, const uint8_t *cls_of_w32, bool use_table, int lds_bytes,
-                        int num_cu, hipStream_t s);
+                        const uint64_t *b_base, const uint8_t *cls_of_w32, int num_cu, hipStream_t s);
 
 }  // namespace gf2x

@@ -1,5 +1,8 @@
-// gf2x_kernels.hip -- kernels of the bit-packed path and their launchers.
-// The per-product work and the size classes live in gf2x_product.hpp.
+// gf2x_kernels.hip -- host side of the bit-packed path: the size-class table,
+// the launchers, and the small helper kernels.  The per-product kernels are
+// instantiated in gf2x_kern_d<G>.hip (direct classes and the mixed-class
+// kernels) and gf2x_kern_staged.hip; the per-product work lives in
+// gf2x_product.hpp.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -7,62 +10,10 @@
 #include <map>
 #include <mutex>
 
+#include "gf2x_launch.hpp"
 #include "gf2x_product.hpp"
 
 namespace gf2x {
-
-template <class Sch>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_per_simd<Sch>()))) void k_single(const uint64_t *a, const uint64_t *b, uint64_t *c, u32 n,
-                                               u32 kind) {
-    extern __shared__ u32 smem[];
-    one_product<Sch>(a, b, c, n, kind, smem);
-}
-
-// Persistent workgroups over a batch whose items all use class Sch.
-template <class Sch>
-__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_per_simd<Sch>()))) void k_batched(const DevItem *items, u32 count, uint64_t *c_base,
-                                                const uint64_t *a_base, const uint64_t *b_base) {
-    extern __shared__ u32 smem[];
-    for (u32 i = blockIdx.x; i < count; i += gridDim.x) {
-        const DevItem it = items[i];
-        one_product<Sch>(a_base + it.a_off, b_base + it.b_off, c_base + it.c_off, it.n, it.kind, smem);
-    }
-}
-
-// Persistent workgroups over a batch of mixed classes; the class of each item
-// comes from its descriptor (host items) or from the per-size table.
-__global__ __launch_bounds__(NT) void k_mixed(const DevItem *items, u32 count, uint64_t *c_base,
-                                              const uint64_t *a_base, const uint64_t *b_base,
-                                              const uint8_t *cls_of_w32, u32 use_table) {
-    extern __shared__ u32 smem[];
-    for (u32 i = blockIdx.x; i < count; i += gridDim.x) {
-        const DevItem it = items[i];
-        if (it.n == 0 || it.n > kMaxBits || it.kind > kKindFull) continue;  // invalid device descriptor
-        const u32 cls = use_table ? (u32)cls_of_w32[(it.n + 31u) / 32u] : it.cls;
-        const uint64_t *a = a_base + it.a_off;
-        const uint64_t *b = b_base + it.b_off;
-        uint64_t *c = c_base + it.c_off;
-        switch (cls) {
-#define GF2X_CASE(id, name, T) \
-    case id: one_product<T>(a, b, c, it.n, it.kind, smem); break;
-            GF2X_CLASS_LIST(GF2X_CASE)
-            default: break;
-        }
-    }
-}
-
-// ----------------------------------------------------------- staged Toom-3
-// Point operands of every item: word w of operand x of point e of item i goes
-// to ws_in[((5 i + e) * 2 + x) * S1 + w].  The parent's words are read from
-// HBM (masked to n bits, zero beyond), split in three parts of m words.
-template <class Top>
-__global__ __launch_bounds__(256) void k_t3_eval(const DevItem *items, u32 count, const uint64_t *a_base,
-                                                 const uint64_t *b_base, u32 *ws_in) {
-    const size_t total = (size_t)count * 10 * Top::S1;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * blockDim.x)
-        ws_in[idx] = t3_eval_word<Top>(items, a_base, b_base, idx);
-}
 
 // Descriptors of the 5 * count point products: full products of S1-word
 // operands (n = 32 S1 bits), operands [a | b] at (5 i + e) * S1 uint64 words
@@ -73,15 +24,6 @@ __global__ void k_child_items(u32 count, u32 S1, u32 child_cls, DevItem *out) {
         const uint64_t base = (uint64_t)j * S1;
         out[j] = DevItem{32u * S1, kKindFull, child_cls, 0u, base, base + S1 / 2, base};
     }
-}
-
-// Interpolation of the five point products of each item, then the ring fold
-// or the full store (persistent workgroups).
-template <class Top>
-__global__ __launch_bounds__(NT) void k_t3_interp(const DevItem *items, u32 count, uint64_t *c_base,
-                                                  const u32 *ws_out) {
-    extern __shared__ u32 smem[];
-    for (u32 i = blockIdx.x; i < count; i += gridDim.x) t3_interp_item<Top>(items[i], c_base, ws_out + (size_t)i * 10 * Top::S1, smem);
 }
 
 // Device descriptors (public layout) -> internal layout; the class is taken
@@ -131,34 +73,41 @@ const ClassInfo &class_info(int cls) { return kClassInfo[cls]; }
 typedef void (*SingleFn)(const uint64_t *, const uint64_t *, uint64_t *, u32, u32);
 typedef void (*BatchedFn)(const DevItem *, u32, uint64_t *, const uint64_t *, const uint64_t *);
 
-#define GF2X_SINGLE_PTR(id, name, T) reinterpret_cast<const void *>(&k_single<T>),
-#define GF2X_BATCHED_PTR(id, name, T) reinterpret_cast<const void *>(&k_batched<T>),
-static const void *kSingle[] = {GF2X_CLASS_LIST(GF2X_SINGLE_PTR)};
-static const void *kBatched[] = {GF2X_CLASS_LIST(GF2X_BATCHED_PTR)};
+static const void *kSingle[kNumDirect];
+static const void *kBatched[kNumDirect];
+static const void *kMixed[kDirectGroups];
+static int kMixedLds[kDirectGroups];  // largest LDS of the classes of each group
+static bool collect_handles() {
+    kMixed[0] = direct_kernels_0(kSingle, kBatched);
+    kMixed[1] = direct_kernels_1(kSingle, kBatched);
+    kMixed[2] = direct_kernels_2(kSingle, kBatched);
+    kMixed[3] = direct_kernels_3(kSingle, kBatched);
+    for (int c = 0; c < kNumDirect; ++c)
+        kMixedLds[c % kDirectGroups] = std::max(kMixedLds[c % kDirectGroups], kClassInfo[c].lds_bytes);
+    return true;
+}
+static const bool kHandlesReady = collect_handles();
 
 static hipError_t set_lds_limit(const void *fn, int bytes) {
     return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
-#define GF2X_INTERP_PTR(id, name, T, c, C) reinterpret_cast<const void *>(&k_t3_interp<T>),
-static const void *kInterp[] = {GF2X_STAGED_LIST(GF2X_INTERP_PTR)};
-
 hipError_t prepare_kernels() {
     (void)kDirectReady;
-#define GF2X_INTERP_ATTR(id, name, T, c, C)                                                               \
-    {                                                                                                     \
-        hipError_t e = set_lds_limit(reinterpret_cast<const void *>(&k_t3_interp<T>), T::INTERP_SCRATCH * 4); \
-        if (e != hipSuccess) return e;                                                                    \
-    }
-    GF2X_STAGED_LIST(GF2X_INTERP_ATTR)
-    (void)kInterp;
+    (void)kHandlesReady;
+    hipError_t e = prepare_staged_kernels();
+    if (e != hipSuccess) return e;
     for (int c = 0; c < kNumDirect; ++c) {
-        hipError_t e = set_lds_limit(kSingle[c], kClassInfo[c].lds_bytes);
+        e = set_lds_limit(kSingle[c], kClassInfo[c].lds_bytes);
         if (e != hipSuccess) return e;
         e = set_lds_limit(kBatched[c], kClassInfo[c].lds_bytes);
         if (e != hipSuccess) return e;
     }
-    return set_lds_limit(reinterpret_cast<const void *>(&k_mixed), 160 * 1024);
+    for (int g = 0; g < kDirectGroups; ++g) {
+        e = set_lds_limit(kMixed[g], kMixedLds[g]);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_single(int cls, const uint64_t *a, const uint64_t *b, uint64_t *c, uint32_t n, uint32_t kind,
@@ -170,7 +119,7 @@ hipError_t launch_single(int cls, const uint64_t *a, const uint64_t *b, uint64_t
 
 // Resident workgroups per CU of a kernel at a given dynamic LDS size (cached:
 // the runtime query is not free and the answer never changes).
-static int occupancy(const void *fn, int lds_bytes) {
+int occupancy(const void *fn, int lds_bytes) {
     static std::mutex mu;
     static std::map<std::pair<const void *, int>, int> cache;
     std::lock_guard<std::mutex> lk(mu);
@@ -202,43 +151,9 @@ size_t staged_workspace_bytes(int cls, uint32_t count) {
     return 2 * ((in + 255) / 256 * 256) + items;
 }
 
-template <class T, int CHILD>
-static hipError_t staged_impl(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
-                              const uint64_t *b_base, void *ws, int num_cu, hipStream_t s) {
-    constexpr int S1 = T::S1;
-    const size_t in_bytes = ((size_t)count * 10 * S1 * 4 + 255) / 256 * 256;
-    u32 *ws_in = reinterpret_cast<u32 *>(ws);
-    u32 *ws_out = reinterpret_cast<u32 *>(reinterpret_cast<char *>(ws) + in_bytes);
-    DevItem *child = reinterpret_cast<DevItem *>(reinterpret_cast<char *>(ws) + 2 * in_bytes);
-    const size_t total = (size_t)count * 10 * S1;
-    const uint32_t eval_grid = (uint32_t)std::min<size_t>((total + 255) / 256, (size_t)num_cu * 16);
-    hipLaunchKernelGGL(k_t3_eval<T>, dim3(eval_grid), dim3(256), 0, s, items, count, a_base, b_base, ws_in);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_child_items, dim3((5 * count + 255) / 256), dim3(256), 0, s, count, (u32)S1, (u32)CHILD,
-                       child);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    e = launch_batched(CHILD, child, 5 * count, reinterpret_cast<uint64_t *>(ws_out),
-                       reinterpret_cast<const uint64_t *>(ws_in), reinterpret_cast<const uint64_t *>(ws_in), num_cu,
-                       s);
-    if (e != hipSuccess) return e;
-    const void *fn = reinterpret_cast<const void *>(&k_t3_interp<T>);
-    const int lds = T::INTERP_SCRATCH * 4;
-    const long long cap = (long long)num_cu * occupancy(fn, lds);
-    const uint32_t grid = (uint32_t)(count < cap ? count : cap);
-    hipLaunchKernelGGL(k_t3_interp<T>, dim3(grid), dim3(NT), lds, s, items, count, c_base, ws_out);
+hipError_t launch_child_items(uint32_t count, uint32_t S1, uint32_t child_cls, DevItem *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_child_items, dim3((5 * count + 255) / 256), dim3(256), 0, s, count, S1, child_cls, out);
     return hipGetLastError();
-}
-
-hipError_t launch_staged(int cls, const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
-                         const uint64_t *b_base, void *ws, int num_cu, hipStream_t s) {
-    switch (cls) {
-#define GF2X_STAGED_CASE(id, name, T, c, C) \
-    case id: return staged_impl<T, c>(items, count, c_base, a_base, b_base, ws, num_cu, s);
-        GF2X_STAGED_LIST(GF2X_STAGED_CASE)
-        default: return hipErrorInvalidValue;
-    }
 }
 
 hipError_t launch_fill_words(uint64_t *dst, size_t count, uint64_t seed, hipStream_t s) {
@@ -251,15 +166,21 @@ hipError_t launch_convert_items(const gf2x_item *items, uint32_t count, DevItem 
     return hipGetLastError();
 }
 
+// One launch per class group, in order on stream s; each skips the items of
+// the other groups.
 hipError_t launch_mixed(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
-                        const uint64_t *b_base, const uint8_t *cls_of_w32, bool use_table, int lds_bytes,
-                        int num_cu, hipStream_t s) {
-    const void *fnp = reinterpret_cast<const void *>(&k_mixed);
-    const long long cap = (long long)num_cu * occupancy(fnp, lds_bytes);
-    const uint32_t grid = (uint32_t)(count < cap ? count : cap);
-    hipLaunchKernelGGL(k_mixed, dim3(grid), dim3(NT), lds_bytes, s, items, count, c_base, a_base, b_base,
-                       cls_of_w32, use_table ? 1u : 0u);
-    return hipGetLastError();
+                        const uint64_t *b_base, const uint8_t *cls_of_w32, int num_cu, hipStream_t s) {
+    typedef void (*MixedFn)(const DevItem *, u32, uint64_t *, const uint64_t *, const uint64_t *, const uint8_t *);
+    for (int g = 0; g < kDirectGroups; ++g) {
+        const long long cap = (long long)num_cu * occupancy(kMixed[g], kMixedLds[g]);
+        const uint32_t grid = (uint32_t)(count < cap ? count : cap);
+        MixedFn fn = reinterpret_cast<MixedFn>(const_cast<void *>(kMixed[g]));
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), kMixedLds[g], s, items, count, c_base, a_base, b_base,
+                           cls_of_w32);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace gf2x

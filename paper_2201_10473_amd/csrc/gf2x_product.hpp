@@ -141,7 +141,7 @@ __device__ __forceinline__ void store_cyclic(const u32 *R, u32 n, uint64_t *c) {
     const u32 s = n % 32u;
     const u32 top = s ? ((1u << s) - 1u) : 0xFFFFFFFFu;
     u32 *c32 = reinterpret_cast<u32 *>(c);
-    for (int k = threadIdx.x; k < out32; k += NT) {
+    for (int k = tid(); k < out32; k += NT) {
         u32 v = 0;
         if (k < w32) {
             const int i0 = k + q, i1 = k + q + 1;
@@ -160,7 +160,7 @@ template <int S>
 __device__ __forceinline__ void store_full(const u32 *R, u32 n, uint64_t *c) {
     const int out32 = 4 * (int)((n + 63u) / 64u);
     u32 *c32 = reinterpret_cast<u32 *>(c);
-    for (int k = threadIdx.x; k < out32; k += NT) c32[k] = k < 2 * S ? R[k] : 0u;
+    for (int k = tid(); k < out32; k += NT) c32[k] = k < 2 * S ? R[k] : 0u;
 }
 
 // Staged Toom-3, evaluation: word idx of the point operands of a batch

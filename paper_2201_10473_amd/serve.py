@@ -48,13 +48,13 @@ def warm_up(srv, seed):
     srv.drain()
 
 
-def run(ctx, rate, count, seed, hbm_budget_bytes=0, streams=0, start_delay_s=0.01, warm=True):
+def run(ctx, rate, count, seed, hbm_budget_bytes=0, streams=0, start_delay_s=0.01, warm=True, max_batch=0):
     """Replay a Poisson process of `count` requests at `rate` per second."""
     ns, off, A, B = make_requests(count, seed)
     C = np.zeros_like(A)
     rng = np.random.default_rng(seed + 1)
     gaps = rng.exponential(1.0 / rate, count)
-    with gf2x.Server(ctx, hbm_budget_bytes=hbm_budget_bytes, streams=streams) as srv:
+    with gf2x.Server(ctx, hbm_budget_bytes=hbm_budget_bytes, streams=streams, max_batch=max_batch) as srv:
         if warm:
             warm_up(srv, seed + 2)
             base = srv.stats()
@@ -116,9 +116,12 @@ def main():
     ap.add_argument("--count", type=int, default=20000)
     ap.add_argument("--seed", type=int, default=inputs.SEED_BASE + 5)
     ap.add_argument("--budget-mib", type=int, default=256)
+    ap.add_argument("--streams", type=int, default=0)
+    ap.add_argument("--max-batch", type=int, default=0)
     args = ap.parse_args()
     with gf2x.Context(0) as ctx:
-        res, bufs = run(ctx, args.rate, args.count, args.seed, args.budget_mib << 20)
+        res, bufs = run(ctx, args.rate, args.count, args.seed, args.budget_mib << 20, args.streams,
+                        max_batch=args.max_batch)
         check_against_batched(ctx, *bufs)
     print(json.dumps(res))
     return 0
