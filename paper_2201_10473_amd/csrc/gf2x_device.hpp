@@ -401,7 +401,7 @@ struct ParK2 {
         }
     }
 
-    __device__ __forceinline__ static u32 *run_ab(const u32 *ab, u32 *scratch) { return run_src(LdsSource{ab, S}, scratch); }
+    __device__ __forceinline__ static u32 *run_ab(u32 *ab, u32 *scratch) { return run_src(LdsSource{ab, S}, scratch); }
 };
 
 // --------------------------------------------------------- workgroup scans
@@ -502,41 +502,46 @@ struct SeqT3 {
     static constexpr int m = S1 - 2;
     static constexpr int S = 3 * m;
     static constexpr int R_WORDS = 6 * m;
+    // R lives in registers: word r of R is held by thread r mod NT.
+    static constexpr int IRW = (R_WORDS + NT - 1) / NT;
     static constexpr int SA_WORDS = 2 * S1 + 2;
     static constexpr int UA_WORDS = 2 * S1 + 2;
     // a Toom-3 child needs its operands materialised (it reads them five
     // times); a Karatsuba child reads them through its root split
     static constexpr int CIN_WORDS = Child::IS_SEQ ? 2 * S1 : 0;
     static constexpr int TMP_WORDS = 2 * NWAVE;
-    static constexpr int SCRATCH = R_WORDS + SA_WORDS + UA_WORDS + CIN_WORDS + TMP_WORDS + Child::SCRATCH;
+    // The scan scratch of the final division is taken from the child's
+    // scratch, which is dead by then; the product is written over the
+    // operands [a | b] (2S words = R_WORDS), which are dead too.
+    static_assert(Child::SCRATCH >= TMP_WORDS, "child scratch holds the scan scratch");
+    static constexpr int SCRATCH = SA_WORDS + UA_WORDS + CIN_WORDS + Child::SCRATCH;
     static constexpr long long BASE = 5 * Child::BASE;
     // evaluation 16*S1, absorption 30*S1, divisions 4m, recombination 8m
     static constexpr long long OPS = 5 * Child::OPS + 46LL * S1 + 12LL * m;
 
-    // Fold point product p (2*S1 words) into R and the numerators Sa, Ua.
-    // Only the words of R that receive a nonzero term are visited, and every
-    // new value is computed before any is stored (one LDS round trip).
+    // Fold point product p (2*S1 words) into R (registers) and the numerators
+    // Sa, Ua.  Only the words of R that receive a nonzero term are touched,
+    // and every new numerator word is computed before any is stored.
     template <int E>
-    __device__ __forceinline__ static void absorb(const u32 *p, u32 *R, u32 *Sa, u32 *Ua) {
+    __device__ __forceinline__ static void absorb(const u32 *p, u32 (&R)[IRW], u32 *Sa, u32 *Ua) {
         auto P = [&](int j) -> u32 { return (j >= 0 && j < 2 * S1) ? p[j] : 0u; };
         // R gets P(r) + P(r-m) (point 0), P(r-m) (point 1), P(r-m) + P(r-4m) (point inf)
         constexpr int R_LO = (E == 0 || E == 2 || E == 3) ? 0 : m;
         constexpr int R_HI = (E == 0) ? m + 2 * S1 : (E == 1) ? m + 2 * S1 : (E == 4) ? R_WORDS : 0;
-        constexpr int NR = R_HI - R_LO, IR = (NR + NT - 1) / NT;
         constexpr int NS = (E != 4) ? 2 * S1 : 0, IS = (NS + NT - 1) / NT;
         constexpr int NU = (E != 0) ? UA_WORDS : 0, IU = (NU + NT - 1) / NT;
         static_assert(R_HI <= R_WORDS, "point 0 and 1 terms fit in R");
         const int t = tid();
-        u32 vr[IR > 0 ? IR : 1], vs[IS > 0 ? IS : 1], vu[IU > 0 ? IU : 1];
+        u32 vs[IS > 0 ? IS : 1], vu[IU > 0 ? IU : 1];
+        if constexpr (R_HI > R_LO) {
 #pragma unroll
-        for (int i = 0; i < IR; ++i) {
-            const int r = R_LO + t + i * NT;
-            if (r < R_HI) {
-                u32 v;
-                if constexpr (E == 0) v = P(r) ^ P(r - m);
-                else if constexpr (E == 1) v = P(r - m);
-                else v = P(r - m) ^ P(r - 4 * m);
-                vr[i] = R[r] ^ v;
+            for (int i = 0; i < IRW; ++i) {
+                const int r = t + i * NT;
+                if (r >= R_LO && r < R_HI) {
+                    if constexpr (E == 0) R[i] ^= P(r) ^ P(r - m);
+                    else if constexpr (E == 1) R[i] ^= P(r - m);
+                    else R[i] ^= P(r - m) ^ P(r - 4 * m);
+                }
             }
         }
 #pragma unroll
@@ -557,11 +562,6 @@ struct SeqT3 {
             }
         }
 #pragma unroll
-        for (int i = 0; i < IR; ++i) {
-            const int r = R_LO + t + i * NT;
-            if (r < R_HI) R[r] = vr[i];
-        }
-#pragma unroll
         for (int i = 0; i < IS; ++i) {
             const int k = t + i * NT;
             if (k < NS) Sa[k] = vs[i];
@@ -574,7 +574,7 @@ struct SeqT3 {
     }
 
     template <int E>
-    __device__ __forceinline__ static void point(const u32 *ab, u32 *R, u32 *Sa, u32 *Ua, u32 *cin, u32 *cs) {
+    __device__ __forceinline__ static void point(u32 *ab, u32 (&R)[IRW], u32 *Sa, u32 *Ua, u32 *cin, u32 *cs) {
         const EvalSource<E> src{ab, S, m};
         const u32 *p;
         if constexpr (Child::IS_SEQ) {
@@ -591,17 +591,35 @@ struct SeqT3 {
         __syncthreads();
     }
 
+    // Final division and recombination: Sa <- c3, Ua <- c2 (first 2m words),
+    // then out[r] = R[r] + c2 (Y + Y^2) + c3 (Y + Y^3) at word r.
+    __device__ __forceinline__ static void finish(const u32 (&R)[IRW], u32 *Sa, u32 *Ua, u32 *tmp, u32 *out) {
+        div_xx1_pair<2 * m>(Sa, Ua, tmp);
+        auto c3 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Sa[j] : 0u; };
+        auto c2 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Ua[j] : 0u; };
+        const int t = tid();
+#pragma unroll
+        for (int i = 0; i < IRW; ++i) {
+            const int r = t + i * NT;
+            if (r < R_WORDS) out[r] = R[i] ^ c2(r - m) ^ c2(r - 2 * m) ^ c3(r - m) ^ c3(r - 3 * m);
+        }
+        __syncthreads();
+    }
+
     // Interpolation only: the five point products (2*S1 words each, in order
     // 0, 1, x, x+1, inf) were computed elsewhere and sit at products (any
     // address space).  scratch needs INTERP_SCRATCH words; returns the 2S-word
     // product inside scratch.
     static constexpr int INTERP_SCRATCH = R_WORDS + SA_WORDS + UA_WORDS + TMP_WORDS;
     __device__ __forceinline__ static u32 *interp_from(const u32 *products, u32 *scratch) {
-        u32 *R = scratch;
-        u32 *Sa = R + R_WORDS;
+        u32 *out = scratch;
+        u32 *Sa = out + R_WORDS;
         u32 *Ua = Sa + SA_WORDS;
         u32 *tmp = Ua + UA_WORDS;
-        for (int k = tid(); k < R_WORDS + SA_WORDS + UA_WORDS; k += NT) R[k] = 0;
+        u32 R[IRW];
+#pragma unroll
+        for (int i = 0; i < IRW; ++i) R[i] = 0;
+        for (int k = tid(); k < SA_WORDS + UA_WORDS; k += NT) Sa[k] = 0;
         __syncthreads();
         absorb<0>(products + 0 * 2 * S1, R, Sa, Ua);
         __syncthreads();
@@ -613,12 +631,8 @@ struct SeqT3 {
         __syncthreads();
         absorb<4>(products + 4 * 2 * S1, R, Sa, Ua);
         __syncthreads();
-        div_xx1_pair<2 * m>(Sa, Ua, tmp);
-        auto c3 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Sa[j] : 0u; };
-        auto c2 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Ua[j] : 0u; };
-        par_map<R_WORDS>(R, [&](int r) -> u32 { return R[r] ^ c2(r - m) ^ c2(r - 2 * m) ^ c3(r - m) ^ c3(r - 3 * m); });
-        __syncthreads();
-        return R;
+        finish(R, Sa, Ua, tmp, out);
+        return out;
     }
 
     // Word w of operand x of point e, from a source of the parent's words.
@@ -633,27 +647,25 @@ struct SeqT3 {
         }
     }
 
-    // ab: [a (S) | b (S)] in LDS; returns the 2S-word product (inside scratch).
-    __device__ __forceinline__ static u32 *run_ab(const u32 *ab, u32 *scratch) {
-        u32 *R = scratch;
-        u32 *Sa = R + R_WORDS;
+    // ab: [a (S) | b (S)] in LDS.  Returns the 2S-word product, written over
+    // ab (whose words are dead once the last point has been evaluated).
+    __device__ __forceinline__ static u32 *run_ab(u32 *ab, u32 *scratch) {
+        u32 *Sa = scratch;
         u32 *Ua = Sa + SA_WORDS;
         u32 *cin = Ua + UA_WORDS;
-        u32 *tmp = cin + CIN_WORDS;
-        u32 *cs = tmp + TMP_WORDS;
-        for (int k = tid(); k < R_WORDS + SA_WORDS + UA_WORDS; k += NT) R[k] = 0;
+        u32 *cs = cin + CIN_WORDS;
+        u32 R[IRW];
+#pragma unroll
+        for (int i = 0; i < IRW; ++i) R[i] = 0;
+        for (int k = tid(); k < SA_WORDS + UA_WORDS; k += NT) Sa[k] = 0;
         // (the barriers inside the first child run order these stores before any absorb)
         point<0>(ab, R, Sa, Ua, cin, cs);
         point<1>(ab, R, Sa, Ua, cin, cs);
         point<2>(ab, R, Sa, Ua, cin, cs);
         point<3>(ab, R, Sa, Ua, cin, cs);
         point<4>(ab, R, Sa, Ua, cin, cs);
-        div_xx1_pair<2 * m>(Sa, Ua, tmp);  // Sa <- c3, Ua <- c2 (first 2m words)
-        auto c3 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Sa[j] : 0u; };
-        auto c2 = [&](int j) -> u32 { return (j >= 0 && j < 2 * m) ? Ua[j] : 0u; };
-        par_map<R_WORDS>(R, [&](int r) -> u32 { return R[r] ^ c2(r - m) ^ c2(r - 2 * m) ^ c3(r - m) ^ c3(r - 3 * m); });
-        __syncthreads();
-        return R;
+        finish(R, Sa, Ua, cs, ab);
+        return ab;
     }
 };
 
