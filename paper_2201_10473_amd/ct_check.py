@@ -6,7 +6,8 @@ operand bits are.  `run` launches the same workload once per operand class
 (all-zero, all-one, random, sparse) -- a 1024-item batch of ring products at
 each ring size, one single-product launch, and one shared-operand Toeplitz
 batch -- and `analyze` compares the instruction counters rocprofv3 recorded for
-those dispatches; every counter must be equal across the four classes.
+those dispatches, kernel by kernel; every counter must be equal across the
+four classes.
 
     rocprofv3 --pmc SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD \\
         SQ_INSTS_VMEM_WR SQ_INSTS_SMEM SQ_INSTS_BRANCH SQ_INSTS_LDS_ATOMIC \\
@@ -93,22 +94,30 @@ def analyze(path):
         d = int(r["Dispatch_Id"])
         by_dispatch.setdefault(d, {"kernel": r["Kernel_Name"].split("(")[0]})[r["Counter_Name"]] = float(
             r["Counter_Value"])
-    dispatches = [by_dispatch[d] for d in sorted(by_dispatch)]
-    if len(dispatches) % 4:
-        print("unexpected dispatch count %d" % len(dispatches))
-        return 1
+    # A workload may launch several kernels (the staged classes launch four),
+    # so the dispatches are grouped per kernel: each launch of a workload runs
+    # every one of its kernels once, in the order zero, ones, random, sparse.
+    per_kernel = {}
+    for d in sorted(by_dispatch):
+        per_kernel.setdefault(by_dispatch[d]["kernel"], []).append(by_dispatch[d])
+    for kern, lst in per_kernel.items():
+        if len(lst) % 4:
+            print("unexpected dispatch count %d for %s" % (len(lst), kern))
+            return 1
     ok = True
-    counters = sorted(k for k in dispatches[0] if k != "kernel")
+    counters = sorted(k for k in next(iter(per_kernel.values()))[0] if k != "kernel")
     print("| workload kernel | counter | zero | ones | random | sparse | equal |")
     print("|---|---|---|---|---|---|---|")
-    for g in range(0, len(dispatches), 4):
-        grp = dispatches[g:g + 4]
-        kern = grp[0]["kernel"].replace("void ", "")
-        for c in counters:
-            vals = [x.get(c) for x in grp]
-            eq = len(set(vals)) == 1
-            ok &= eq
-            print("| %s | %s | %s | %s | %s | %s | %s |" % (kern[:60], c, *["%.0f" % v for v in vals], "yes" if eq else "NO"))
+    for kern, lst in per_kernel.items():
+        for g in range(0, len(lst), 4):
+            grp = lst[g:g + 4]
+            name = kern.replace("void ", "")
+            for c in counters:
+                vals = [x.get(c) for x in grp]
+                eq = len(set(vals)) == 1
+                ok &= eq
+                print("| %s | %s | %s | %s | %s | %s | %s |" % (name[:60], c, *["%.0f" % v for v in vals],
+                                                               "yes" if eq else "NO"))
     print("ALL EQUAL" if ok else "MISMATCH")
     return 0 if ok else 1
 
