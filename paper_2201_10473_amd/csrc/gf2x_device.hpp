@@ -498,6 +498,7 @@ struct EvalSource {
 template <class Child>
 struct SeqT3 {
     static constexpr bool IS_SEQ = true;
+    static constexpr int NP = 5;  // point products
     static constexpr int S1 = Child::S;
     static constexpr int m = S1 - 2;
     static constexpr int S = 3 * m;
@@ -666,6 +667,177 @@ struct SeqT3 {
         point<4>(ab, R, Sa, Ua, cin, cs);
         finish(R, Sa, Ua, cs, ab);
         return ab;
+    }
+};
+
+// ------------------------------------------------------ strided prefix XOR
+// x[k] <- x[k] + x[k-s] + x[k-2s] + ... for 0 <= k < L (s = STRIDE): exact
+// division by 1 + x^s of a polynomial in x = X^32 given by its words, from
+// the low end (the division by x + 1 of Section 3.2, generalised to x^s + 1).
+// Each thread scans a block of C consecutive words (C a multiple of s, so
+// the chain k mod s of a word is its offset mod s), then the block totals of
+// the s chains are scanned across the workgroup.  tmp: NWAVE*STRIDE words.
+// Ends with a barrier.
+template <int L, int STRIDE>
+__device__ __forceinline__ void scan_xor_stride(u32 *x, u32 *tmp) {
+    constexpr int C = STRIDE * ((L + NT * STRIDE - 1) / (NT * STRIDE));
+    const int t = tid();
+    u32 v[C], acc[STRIDE], tot[STRIDE];
+#pragma unroll
+    for (int c = 0; c < STRIDE; ++c) acc[c] = 0;
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        const int k = t * C + i;
+        acc[i % STRIDE] ^= (k < L) ? x[k] : 0u;
+        v[i] = acc[i % STRIDE];
+    }
+#pragma unroll
+    for (int c = 0; c < STRIDE; ++c) tot[c] = acc[c];
+    const int lane = t & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+        for (int c = 0; c < STRIDE; ++c) {
+            const u32 o = __shfl_up(acc[c], d, 64);
+            if (lane >= d) acc[c] ^= o;
+        }
+    }
+    const int wave = t >> 6;
+    if (lane == 63) {
+#pragma unroll
+        for (int c = 0; c < STRIDE; ++c) tmp[wave * STRIDE + c] = acc[c];
+    }
+    __syncthreads();
+    u32 pre[STRIDE];  // exclusive prefix of this thread's block, per chain
+#pragma unroll
+    for (int c = 0; c < STRIDE; ++c) {
+        pre[c] = acc[c] ^ tot[c];
+        for (int w = 0; w < wave; ++w) pre[c] ^= tmp[w * STRIDE + c];
+    }
+#pragma unroll
+    for (int i = 0; i < C; ++i) {
+        const int k = t * C + i;
+        if (k < L) x[k] = v[i] ^ pre[i % STRIDE];
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------- Toom-Cook 4
+// Word-aligned Toom-Cook 4 with x = X^32 (the four-way split that the
+// Toom-Cook complexity table of Section 3 lists for operands above 346
+// 64-bit words), used as the staged top level only.  Operands of S = 4m words
+// split as a = a0 + a1 Y + a2 Y^2 + a3 Y^3, Y = X^{32m}.  Seven points, in
+// this order:
+//   0, 1, x, z = x+1, 1/x, 1/z, inf,
+// the two reciprocal points homogenised (x^3 a(1/x), z^3 a(1/z)) so that
+// every point operand is a polynomial of at most m + 3 words: S1 = m + 3.
+//
+// Interpolation.  With c(Y) = c0 + Y P(Y) + c6 Y^6, P(t) = c1 + c2 t + ... +
+// c5 t^4, the symmetric sums E(t) = P(t) + t^4 P(1/t) only involve
+// u = c1 + c5 and v = c2 + c4:  E(t) = u (1+t)^4 + v t (1+t)^2, so that
+// E(x) and E(z) (note 1 + z = x) give
+//   u = (x E(x) + z E(z)) / (x (x^3 + 1)),   v = (x E(x) + (x + x^5) u) / (x^2 (x^2 + 1)),
+// then c3 = C(1) + c0 + c6 + u + v.  The same two-point system in G(t) =
+// P(t) + c3 t^2 + v t^3 + u t^4 = c1 (1+t)^4 + c2 t (1+t)^2 gives c1 and c2,
+// and c5 = u + c1, c4 = v + c2.  Every division is exact; division by x^s is
+// a word shift and by x^s + 1 a strided prefix XOR (scan_xor_stride), with
+// s = 3 (x^3 + 1 = (x + 1)(x^2 + x + 1)) and s = 2 ((x + 1)^2 = x^2 + 1).
+template <class Child>
+struct TopT4 {
+    static constexpr bool IS_SEQ = true;
+    static constexpr int NP = 7;
+    static constexpr int S1 = Child::S;
+    static constexpr int m = S1 - 3;
+    static constexpr int S = 4 * m;
+    static constexpr int L = 2 * m;  // words of each coefficient c_i
+    static constexpr int TMP_WORDS = 3 * NWAVE;
+    // u, v, c3, c1, c2 (L words each), the product (2S words), scan scratch
+    static constexpr int INTERP_SCRATCH = 5 * L + 2 * S + TMP_WORDS;
+    static constexpr long long BASE = 7 * Child::BASE;
+    // evaluation 50*S1 (25 XORs per word of each operand), interpolation
+    // about 39 XORs per coefficient word and 6 per product word
+    static constexpr long long OPS = 7 * Child::OPS + 50LL * S1 + 126LL * m;
+
+    // Word w of operand x of point e, from a source of the parent's words.
+    template <class Part>
+    __device__ __forceinline__ static u32 point_word(int e, int x, int w, const Part &part) {
+        auto p = [&](int q, int j) -> u32 { return part(x, q, j); };
+        switch (e) {
+            case 0: return p(0, w);
+            case 1: return p(0, w) ^ p(1, w) ^ p(2, w) ^ p(3, w);
+            case 2: return p(0, w) ^ p(1, w - 1) ^ p(2, w - 2) ^ p(3, w - 3);
+            case 3:  // a0 + a1 (x+1) + a2 (x^2+1) + a3 (x^3+x^2+x+1)
+                return p(0, w) ^ p(1, w) ^ p(1, w - 1) ^ p(2, w) ^ p(2, w - 2) ^ p(3, w) ^ p(3, w - 1) ^ p(3, w - 2) ^
+                       p(3, w - 3);
+            case 4: return p(0, w - 3) ^ p(1, w - 2) ^ p(2, w - 1) ^ p(3, w);
+            case 5:  // a0 z^3 + a1 z^2 + a2 z + a3
+                return p(0, w) ^ p(0, w - 1) ^ p(0, w - 2) ^ p(0, w - 3) ^ p(1, w) ^ p(1, w - 2) ^ p(2, w) ^ p(2, w - 1) ^
+                       p(3, w);
+            default: return p(3, w);
+        }
+    }
+
+    // The seven point products (2*S1 words each, in point order) sit at
+    // products (any address space).  scratch needs INTERP_SCRATCH words;
+    // returns the 2S-word product inside scratch.
+    __device__ __forceinline__ static u32 *interp_from(const u32 *products, u32 *scratch) {
+        u32 *U = scratch;
+        u32 *V = U + L;
+        u32 *C3 = V + L;
+        u32 *C1 = C3 + L;
+        u32 *C2 = C1 + L;
+        u32 *out = C2 + L;
+        u32 *tmp = out + 2 * S;
+        // word j of point product e, and of a coefficient array, zero outside
+        auto P = [&](int e, int j) -> u32 { return (j >= 0 && j < 2 * S1) ? products[e * 2 * S1 + j] : 0u; };
+        auto A = [&](const u32 *c, int j) -> u32 { return (j >= 0 && j < L) ? c[j] : 0u; };
+        auto s06 = [&](int j) -> u32 { return P(0, j) ^ P(6, j); };
+        const int t = tid();
+        // u: (x E(x) + z E(z)) / x, then / (x^3 + 1)
+        for (int k = t; k < L; k += NT) {
+            const int j = k + 1;
+            U[k] = P(2, j) ^ P(4, j) ^ P(3, j) ^ P(5, j) ^ s06(j) ^ s06(j - 2) ^ s06(j - 4);
+        }
+        __syncthreads();
+        scan_xor_stride<L, 3>(U, tmp);
+        // v: (x E(x) + (x + x^5) u) / x^2, then / (x^2 + 1)
+        for (int k = t; k < L; k += NT) {
+            const int j = k + 2;
+            V[k] = P(2, j) ^ P(4, j) ^ s06(j) ^ s06(j - 6) ^ A(U, j - 1) ^ A(U, j - 5);
+        }
+        __syncthreads();
+        scan_xor_stride<L, 2>(V, tmp);
+        for (int k = t; k < L; k += NT) C3[k] = P(1, k) ^ s06(k) ^ U[k] ^ V[k];
+        __syncthreads();
+        // c1: (x G(x) + z G(z)) / x, then / (x^3 + 1)
+        for (int k = t; k < L; k += NT) {
+            const int j = k + 1;
+            C1[k] = P(2, j) ^ P(3, j) ^ P(6, j) ^ P(6, j - 2) ^ P(6, j - 4) ^ A(C3, j) ^ A(C3, j - 1) ^ A(C3, j - 2) ^
+                    A(V, j) ^ A(U, j) ^ A(U, j - 1) ^ A(U, j - 4);
+        }
+        __syncthreads();
+        scan_xor_stride<L, 3>(C1, tmp);
+        // c2: (x G(x) + (x + x^5) c1) / x^2, then / (x^2 + 1)
+        for (int k = t; k < L; k += NT) {
+            const int j = k + 2;
+            C2[k] = P(2, j) ^ P(0, j) ^ P(6, j - 6) ^ A(C3, j - 3) ^ A(V, j - 4) ^ A(U, j - 5) ^ A(C1, j - 1) ^
+                    A(C1, j - 5);
+        }
+        __syncthreads();
+        scan_xor_stride<L, 2>(C2, tmp);
+        // recomposition: c0 + c1 Y + ... + c6 Y^6, c4 = v + c2, c5 = u + c1
+        for (int r = t; r < 2 * S; r += NT) {
+            u32 w = (r < L) ? P(0, r) : 0u;
+            w ^= A(C1, r - m);
+            w ^= A(C2, r - 2 * m);
+            w ^= A(C3, r - 3 * m);
+            w ^= A(V, r - 4 * m) ^ A(C2, r - 4 * m);
+            w ^= A(U, r - 5 * m) ^ A(C1, r - 5 * m);
+            w ^= (r - 6 * m >= 0 && r - 6 * m < L) ? P(6, r - 6 * m) : 0u;
+            out[r] = w;
+        }
+        __syncthreads();
+        return out;
     }
 };
 

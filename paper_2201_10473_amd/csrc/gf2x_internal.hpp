@@ -11,7 +11,7 @@
 namespace gf2x {
 
 constexpr int kNumDirect = 25;   // classes computed inside one workgroup
-constexpr int kNumClasses = 31;  // plus the staged classes
+constexpr int kNumClasses = 34;  // plus the staged classes
 constexpr uint32_t kKindCyclic = 0;
 constexpr uint32_t kKindFull = 1;
 constexpr uint32_t kMaxBits = 131072;
@@ -35,6 +35,7 @@ struct ClassInfo {
     long long ops;           // algorithmic VALU lane-ops per multiplication
     int child;               // staged: class of the five point products; else -1
     int direct;              // class computing the same size inside one workgroup
+    int points;              // staged: point products per item (5 or 7); else 0
 };
 
 const ClassInfo &class_info(int cls);

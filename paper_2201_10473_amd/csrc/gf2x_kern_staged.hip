@@ -1,6 +1,6 @@
-// gf2x_kern_staged.hip -- staged Toom-3 classes: the top Toom-3 level is
+// gf2x_kern_staged.hip -- staged classes: the top Toom-3 or Toom-4 level is
 // spread over workgroups through HBM (evaluation kernel, one batched launch
-// of the 5 * count point products, interpolation kernel).
+// of the NP * count point products, interpolation kernel).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -12,30 +12,31 @@
 namespace gf2x {
 
 // Point operands of every item: word w of operand x of point e of item i goes
-// to ws_in[((5 i + e) * 2 + x) * S1 + w].  The parent's words are read from
-// HBM (masked to n bits, zero beyond), split in three parts of m words.
+// to ws_in[((NP i + e) * 2 + x) * S1 + w].  The parent's words are read from
+// HBM (masked to n bits, zero beyond), split in parts of m words.
 template <class Top>
-__global__ __launch_bounds__(256) void k_t3_eval(const DevItem *items, u32 count, const uint64_t *a_base,
-                                                 const uint64_t *b_base, u32 *ws_in) {
-    const size_t total = (size_t)count * 10 * Top::S1;
+__global__ __launch_bounds__(256) void k_stage_eval(const DevItem *items, u32 count, const uint64_t *a_base,
+                                                    const uint64_t *b_base, u32 *ws_in) {
+    const size_t total = (size_t)count * 2 * Top::NP * Top::S1;
     for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x)
-        ws_in[idx] = t3_eval_word<Top>(items, a_base, b_base, idx);
+        ws_in[idx] = staged_eval_word<Top>(items, a_base, b_base, idx);
 }
 
-// Interpolation of the five point products of each item, then the ring fold
+// Interpolation of the NP point products of each item, then the ring fold
 // or the full store (persistent workgroups).
 template <class Top>
-__global__ __launch_bounds__(NT) void k_t3_interp(const DevItem *items, u32 count, uint64_t *c_base,
-                                                  const u32 *ws_out) {
+__global__ __launch_bounds__(NT) void k_stage_interp(const DevItem *items, u32 count, uint64_t *c_base,
+                                                     const u32 *ws_out) {
     extern __shared__ u32 smem[];
-    for (u32 i = blockIdx.x; i < count; i += gridDim.x) t3_interp_item<Top>(items[i], c_base, ws_out + (size_t)i * 10 * Top::S1, smem);
+    for (u32 i = blockIdx.x; i < count; i += gridDim.x)
+        staged_interp_item<Top>(items[i], c_base, ws_out + (size_t)i * 2 * Top::NP * Top::S1, smem);
 }
 
 hipError_t prepare_staged_kernels() {
 #define GF2X_INTERP_ATTR(id, name, T, c, C)                                                                    \
     {                                                                                                          \
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_t3_interp<T>),                   \
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stage_interp<T>),                   \
                                            hipFuncAttributeMaxDynamicSharedMemorySize, T::INTERP_SCRATCH * 4); \
         if (e != hipSuccess) return e;                                                                         \
     }
@@ -46,27 +47,27 @@ hipError_t prepare_staged_kernels() {
 template <class T, int CHILD>
 static hipError_t staged_impl(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
                               const uint64_t *b_base, void *ws, int num_cu, hipStream_t s) {
-    constexpr int S1 = T::S1;
-    const size_t in_bytes = ((size_t)count * 10 * S1 * 4 + 255) / 256 * 256;
+    constexpr int S1 = T::S1, NP = T::NP;
+    const size_t in_bytes = ((size_t)count * 2 * NP * S1 * 4 + 255) / 256 * 256;
     u32 *ws_in = reinterpret_cast<u32 *>(ws);
     u32 *ws_out = reinterpret_cast<u32 *>(reinterpret_cast<char *>(ws) + in_bytes);
     DevItem *child = reinterpret_cast<DevItem *>(reinterpret_cast<char *>(ws) + 2 * in_bytes);
-    const size_t total = (size_t)count * 10 * S1;
+    const size_t total = (size_t)count * 2 * NP * S1;
     const uint32_t eval_grid = (uint32_t)std::min<size_t>((total + 255) / 256, (size_t)num_cu * 16);
-    hipLaunchKernelGGL(k_t3_eval<T>, dim3(eval_grid), dim3(256), 0, s, items, count, a_base, b_base, ws_in);
+    hipLaunchKernelGGL(k_stage_eval<T>, dim3(eval_grid), dim3(256), 0, s, items, count, a_base, b_base, ws_in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = launch_child_items(count, (u32)S1, (u32)CHILD, child, s);
+    e = launch_child_items(count, (u32)S1, (u32)NP, (u32)CHILD, child, s);
     if (e != hipSuccess) return e;
-    e = launch_batched(CHILD, child, 5 * count, reinterpret_cast<uint64_t *>(ws_out),
+    e = launch_batched(CHILD, child, NP * count, reinterpret_cast<uint64_t *>(ws_out),
                        reinterpret_cast<const uint64_t *>(ws_in), reinterpret_cast<const uint64_t *>(ws_in), num_cu,
                        s);
     if (e != hipSuccess) return e;
-    const void *fn = reinterpret_cast<const void *>(&k_t3_interp<T>);
+    const void *fn = reinterpret_cast<const void *>(&k_stage_interp<T>);
     const int lds = T::INTERP_SCRATCH * 4;
     const long long cap = (long long)num_cu * occupancy(fn, lds);
     const uint32_t grid = (uint32_t)(count < cap ? count : cap);
-    hipLaunchKernelGGL(k_t3_interp<T>, dim3(grid), dim3(NT), lds, s, items, count, c_base, ws_out);
+    hipLaunchKernelGGL(k_stage_interp<T>, dim3(grid), dim3(NT), lds, s, items, count, c_base, ws_out);
     return hipGetLastError();
 }
 

@@ -15,12 +15,12 @@
 
 namespace gf2x {
 
-// Descriptors of the 5 * count point products: full products of S1-word
-// operands (n = 32 S1 bits), operands [a | b] at (5 i + e) * S1 uint64 words
-// of ws_in, results at (5 i + e) * S1 words of ws_out.
-__global__ void k_child_items(u32 count, u32 S1, u32 child_cls, DevItem *out) {
+// Descriptors of the np * count point products: full products of S1-word
+// operands (n = 32 S1 bits), operands [a | b] at (np i + e) * S1 uint64 words
+// of ws_in, results at (np i + e) * S1 words of ws_out.
+__global__ void k_child_items(u32 count, u32 S1, u32 np, u32 child_cls, DevItem *out) {
     const u32 j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < 5 * count) {
+    if (j < np * count) {
         const uint64_t base = (uint64_t)j * S1;
         out[j] = DevItem{32u * S1, kKindFull, child_cls, 0u, base, base + S1 / 2, base};
     }
@@ -48,19 +48,24 @@ __global__ void k_fill_words(uint64_t *dst, size_t count, uint64_t seed) {
 
 // ------------------------------------------------------------ host side
 #define GF2X_INFO(id, name, T) \
-    {id, name, T::S, lds_words<T>() * 4, T::BASE, T::OPS, -1, id},
+    {id, name, T::S, lds_words<T>() * 4, T::BASE, T::OPS, -1, id, 0},
 #define GF2X_STAGED_INFO(id, name, T, c, C)                                                             \
     {id, name, T::S, (lds_words<C>() > T::INTERP_SCRATCH ? lds_words<C>() : T::INTERP_SCRATCH) * 4, T::BASE, \
-     T::OPS, c, -2},
+     T::OPS, c, -2, T::NP},
 static ClassInfo kClassInfo[] = {GF2X_CLASS_LIST(GF2X_INFO) GF2X_STAGED_LIST(GF2X_STAGED_INFO)};
 
-// the direct class of each staged class is the one with the same top schedule
+// The direct class of a staged class is the one with the same top schedule;
+// a top level that exists only staged (Toom-4) takes the cheapest direct
+// class that holds its size.
 static int find_direct(int id) {
     const ClassInfo &ci = kClassInfo[id];
     if (ci.direct != -2) return ci.direct;
     for (int c = 0; c < kNumDirect; ++c)
         if (kClassInfo[c].S == ci.S && kClassInfo[c].ops == ci.ops) return c;
-    return -1;
+    int best = -1;
+    for (int c = 0; c < kNumDirect; ++c)
+        if (kClassInfo[c].S >= ci.S && (best < 0 || kClassInfo[c].ops < kClassInfo[best].ops)) best = c;
+    return best;
 }
 static bool init_direct() {
     for (int c = 0; c < kNumClasses; ++c) kClassInfo[c].direct = find_direct(c);
@@ -147,12 +152,15 @@ size_t staged_workspace_bytes(int cls, uint32_t count) {
     const ClassInfo &ci = kClassInfo[cls];
     if (ci.child < 0) return 0;
     const size_t S1 = (size_t)kClassInfo[ci.child].S;
-    const size_t in = (size_t)count * 10 * S1 * 4, items = (size_t)count * 5 * sizeof(DevItem);
+    const size_t np = (size_t)ci.points;
+    const size_t in = (size_t)count * 2 * np * S1 * 4, items = (size_t)count * np * sizeof(DevItem);
     return 2 * ((in + 255) / 256 * 256) + items;
 }
 
-hipError_t launch_child_items(uint32_t count, uint32_t S1, uint32_t child_cls, DevItem *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_child_items, dim3((5 * count + 255) / 256), dim3(256), 0, s, count, S1, child_cls, out);
+hipError_t launch_child_items(uint32_t count, uint32_t S1, uint32_t np, uint32_t child_cls, DevItem *out,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_child_items, dim3((np * count + 255) / 256), dim3(256), 0, s, count, S1, np, child_cls,
+                       out);
     return hipGetLastError();
 }
 

@@ -26,7 +26,8 @@ hipError_t prepare_staged_kernels();
 // Resident workgroups per CU of kernel fn at a dynamic LDS size (cached).
 int occupancy(const void *fn, int lds_bytes);
 
-// Descriptors of the five point products of count staged items.
-hipError_t launch_child_items(uint32_t count, uint32_t S1, uint32_t child_cls, DevItem *out, hipStream_t s);
+// Descriptors of the np point products of each of count staged items.
+hipError_t launch_child_items(uint32_t count, uint32_t S1, uint32_t np, uint32_t child_cls, DevItem *out,
+                              hipStream_t s);
 
 }  // namespace gf2x

@@ -48,6 +48,10 @@ using Class21 = SeqT3<ParK2<5, 7>>;
 using Class22 = SeqT3<ParK2<5, 4>>;
 using Class23 = ParK2<5, 6>;
 using Class24 = ParK2<5, 9>;
+// top levels that exist only as staged classes
+using Top4Class9 = TopT4<Class9>;
+using Top4Class22 = TopT4<Class22>;
+using Top4Class24 = TopT4<Class24>;
 
 // X(id, name, schedule type)
 #define GF2X_CLASS_LIST(X) \
@@ -77,10 +81,11 @@ using Class24 = ParK2<5, 9>;
     X(23, "K2^5.U6", Class23) \
     X(24, "K2^5.U9", Class24)
 
-// Staged classes: the top Toom-3 level of a class is spread over workgroups.
-// An evaluation kernel writes the five point operands of every product to a
-// workspace, the child class computes all of them as one batch of full
-// products, and an interpolation kernel recombines and folds.
+// Staged classes: the top Toom-3 (5 points) or Toom-4 (7 points) level of a
+// class is spread over workgroups.  An evaluation kernel writes the point
+// operands of every product to a workspace, the child class computes all of
+// them as one batch of full products, and an interpolation kernel recombines
+// and folds.
 // X(id, name, top schedule type, child class id, child schedule type)
 #define GF2X_STAGED_LIST(X) \
     X(25, "G.T3.T3.K2^5.U4", Class14, 22, Class22) \
@@ -88,7 +93,10 @@ using Class24 = ParK2<5, 9>;
     X(27, "G.T3.T3.K2^5.U7", Class17, 21, Class21) \
     X(28, "G.T3.K2^5.U6", Class10, 23, Class23) \
     X(29, "G.T3.K2^5.U9", Class13, 24, Class24) \
-    X(30, "G.T3.T3.T3.K2^5.U5", Class20, 15, Class15)
+    X(30, "G.T3.T3.T3.K2^5.U5", Class20, 15, Class15) \
+    X(31, "G.T4.T3.K2^5.U5", Top4Class9, 9, Class9) \
+    X(32, "G.T4.T3.K2^5.U4", Top4Class22, 22, Class22) \
+    X(33, "G.T4.K2^5.U9", Top4Class24, 24, Class24)
 
 #define GF2X_COUNT_CLASS(id, name, T) +1
 constexpr int NUM_CLASSES = 0 GF2X_CLASS_LIST(GF2X_COUNT_CLASS);
@@ -163,15 +171,16 @@ __device__ __forceinline__ void store_full(const u32 *R, u32 n, uint64_t *c) {
     for (int k = tid(); k < out32; k += NT) c32[k] = k < 2 * S ? R[k] : 0u;
 }
 
-// Staged Toom-3, evaluation: word idx of the point operands of a batch
-// (layout ((5 i + e) * 2 + x) * S1 + w) from the items' operands in HBM,
-// masked to n bits, zero beyond, split in three parts of m words.
+// Staged top level (Toom-3 or Toom-4), evaluation: word idx of the point
+// operands of a batch (layout ((NP i + e) * 2 + x) * S1 + w, NP points per
+// item) from the items' operands in HBM, masked to n bits, zero beyond,
+// split in parts of m words.
 template <class Top>
-__device__ __forceinline__ u32 t3_eval_word(const DevItem *items, const uint64_t *a_base, const uint64_t *b_base,
-                                            size_t idx) {
-    constexpr int S1 = Top::S1, m = Top::m;
-    const u32 i = (u32)(idx / (10 * S1));
-    const int r = (int)(idx - (size_t)i * 10 * S1);
+__device__ __forceinline__ u32 staged_eval_word(const DevItem *items, const uint64_t *a_base, const uint64_t *b_base,
+                                                size_t idx) {
+    constexpr int S1 = Top::S1, m = Top::m, NP = Top::NP;
+    const u32 i = (u32)(idx / (2 * NP * S1));
+    const int r = (int)(idx - (size_t)i * 2 * NP * S1);
     const int e = r / (2 * S1);
     const int x = (r - e * 2 * S1) / S1;
     const int w = r - e * 2 * S1 - x * S1;
@@ -190,10 +199,11 @@ __device__ __forceinline__ u32 t3_eval_word(const DevItem *items, const uint64_t
     return Top::point_word(e, x, w, part);
 }
 
-// Staged Toom-3, interpolation of one item from its five point products
+// Staged top level, interpolation of one item from its NP point products
 // (2*S1 words each, consecutive), then the ring fold or the full store.
 template <class Top>
-__device__ __forceinline__ void t3_interp_item(const DevItem &it, uint64_t *c_base, const u32 *products, u32 *smem) {
+__device__ __forceinline__ void staged_interp_item(const DevItem &it, uint64_t *c_base, const u32 *products,
+                                                   u32 *smem) {
     const u32 *R = Top::interp_from(products, smem);
     if (it.kind == kKindCyclic) store_cyclic<Top::S>(R, it.n, c_base + it.c_off);
     else store_full<Top::S>(R, it.n, c_base + it.c_off);

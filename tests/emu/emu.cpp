@@ -167,7 +167,7 @@ extern "C" int emu_toeplitz(const uint64_t *h, uint32_t n, const uint64_t *R, ui
 }
 
 // Staged class `id` (from the staged list) on one product: evaluation for
-// every point word, the five point products by the child class (emulated
+// every point word, the NP point products by the child class (emulated
 // workgroups, full products), then the interpolation workgroup.
 namespace {
 struct InterpJob {
@@ -183,29 +183,29 @@ void *interp_worker(void *p) {
     threadIdx.x = j->tid;
     int k = 0;
 #define EMU_INTERP(id, name, T, cid, C) \
-    if (k++ == j->which) gf2x::t3_interp_item<gf2x::T>(j->it, j->c, j->products, j->smem);
+    if (k++ == j->which) gf2x::staged_interp_item<gf2x::T>(j->it, j->c, j->products, j->smem);
     GF2X_STAGED_LIST(EMU_INTERP)
     return nullptr;
 }
 }  // namespace
 
 extern "C" int emu_staged(int which, const uint64_t *a, const uint64_t *b, uint64_t *c, uint32_t n, uint32_t kind) {
-    int k = 0, S1 = 0, m = 0, child = -1, interp_words = 0;
+    int k = 0, S1 = 0, m = 0, np = 0, child = -1, interp_words = 0;
 #define EMU_STAGED_INFO(id, name, T, cc, C) \
-    if (k++ == which) { S1 = gf2x::T::S1; m = gf2x::T::m; child = cc; interp_words = gf2x::T::INTERP_SCRATCH; }
+    if (k++ == which) { S1 = gf2x::T::S1; m = gf2x::T::m; np = gf2x::T::NP; child = cc; interp_words = gf2x::T::INTERP_SCRATCH; }
     GF2X_STAGED_LIST(EMU_STAGED_INFO)
     if (child < 0) return -1;
     (void)m;
     gf2x::DevItem it{n, kind, 0u, 0u, 0, 0, 0};
-    std::vector<uint32_t> ws_in(10 * (size_t)S1), ws_out(10 * (size_t)S1);
+    std::vector<uint32_t> ws_in(2 * (size_t)np * S1), ws_out(2 * (size_t)np * S1);
     k = 0;
     for (size_t idx = 0; idx < ws_in.size(); ++idx) {
         int kk = 0;
 #define EMU_EVAL(id, name, T, cc, C) \
-        if (kk++ == which) ws_in[idx] = gf2x::t3_eval_word<gf2x::T>(&it, a, b, idx);
+        if (kk++ == which) ws_in[idx] = gf2x::staged_eval_word<gf2x::T>(&it, a, b, idx);
         GF2X_STAGED_LIST(EMU_EVAL)
     }
-    for (int e = 0; e < 5; ++e) {
+    for (int e = 0; e < np; ++e) {
         const uint64_t *pa = reinterpret_cast<const uint64_t *>(ws_in.data() + (size_t)e * 2 * S1);
         const uint64_t *pb = pa + S1 / 2;
         uint64_t *pc = reinterpret_cast<uint64_t *>(ws_out.data() + (size_t)e * 2 * S1);

@@ -112,6 +112,7 @@ ALL_CLASSES = [
     ("T3.K2^5.U7", 666), ("T3.K2^5.U4", 378), ("K2^5.U6", 192), ("K2^5.U9", 288),
     ("G.T3.T3.K2^5.U4", 1128), ("G.T3.T3.K2^5.U5", 1416), ("G.T3.T3.K2^5.U7", 1992), ("G.T3.K2^5.U6", 570),
     ("G.T3.K2^5.U9", 858), ("G.T3.T3.T3.K2^5.U5", 4242),
+    ("G.T4.T3.K2^5.U5", 1884), ("G.T4.T3.K2^5.U4", 1500), ("G.T4.K2^5.U9", 1140),
 ]
 
 
