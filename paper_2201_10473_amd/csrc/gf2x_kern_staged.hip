@@ -4,23 +4,20 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <algorithm>
-
 #include "gf2x_launch.hpp"
 #include "gf2x_product.hpp"
 
 namespace gf2x {
 
 // Point operands of every item: word w of operand x of point e of item i goes
-// to ws_in[((NP i + e) * 2 + x) * S1 + w].  The parent's words are read from
-// HBM (masked to n bits, zero beyond), split in parts of m words.
+// to ws_in[((NP i + e) * 2 + x) * S1 + w] (persistent workgroups, one item
+// at a time).
 template <class Top>
-__global__ __launch_bounds__(256) void k_stage_eval(const DevItem *items, u32 count, const uint64_t *a_base,
-                                                    const uint64_t *b_base, u32 *ws_in) {
-    const size_t total = (size_t)count * 2 * Top::NP * Top::S1;
-    for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * blockDim.x)
-        ws_in[idx] = staged_eval_word<Top>(items, a_base, b_base, idx);
+__global__ __launch_bounds__(NT) void k_stage_eval(const DevItem *items, u32 count, const uint64_t *a_base,
+                                                   const uint64_t *b_base, u32 *ws_in) {
+    extern __shared__ u32 smem[];
+    for (u32 i = blockIdx.x; i < count; i += gridDim.x)
+        staged_eval_item<Top>(items[i], a_base, b_base, ws_in + (size_t)i * 2 * Top::NP * Top::S1, smem);
 }
 
 // Interpolation of the NP point products of each item, then the ring fold
@@ -39,6 +36,9 @@ hipError_t prepare_staged_kernels() {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stage_interp<T>),                   \
                                            hipFuncAttributeMaxDynamicSharedMemorySize, T::INTERP_SCRATCH * 4); \
         if (e != hipSuccess) return e;                                                                         \
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stage_eval<T>),                               \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 2 * T::S * 4);                     \
+        if (e != hipSuccess) return e;                                                                         \
     }
     GF2X_STAGED_LIST(GF2X_INTERP_ATTR)
     return hipSuccess;
@@ -52,9 +52,11 @@ static hipError_t staged_impl(const DevItem *items, uint32_t count, uint64_t *c_
     u32 *ws_in = reinterpret_cast<u32 *>(ws);
     u32 *ws_out = reinterpret_cast<u32 *>(reinterpret_cast<char *>(ws) + in_bytes);
     DevItem *child = reinterpret_cast<DevItem *>(reinterpret_cast<char *>(ws) + 2 * in_bytes);
-    const size_t total = (size_t)count * 2 * NP * S1;
-    const uint32_t eval_grid = (uint32_t)std::min<size_t>((total + 255) / 256, (size_t)num_cu * 16);
-    hipLaunchKernelGGL(k_stage_eval<T>, dim3(eval_grid), dim3(256), 0, s, items, count, a_base, b_base, ws_in);
+    const void *efn = reinterpret_cast<const void *>(&k_stage_eval<T>);
+    const int elds = 2 * T::S * 4;
+    const long long ecap = (long long)num_cu * occupancy(efn, elds);
+    const uint32_t eval_grid = (uint32_t)(count < ecap ? count : ecap);
+    hipLaunchKernelGGL(k_stage_eval<T>, dim3(eval_grid), dim3(NT), elds, s, items, count, a_base, b_base, ws_in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = launch_child_items(count, (u32)S1, (u32)NP, (u32)CHILD, child, s);

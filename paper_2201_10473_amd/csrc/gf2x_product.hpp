@@ -171,32 +171,24 @@ __device__ __forceinline__ void store_full(const u32 *R, u32 n, uint64_t *c) {
     for (int k = tid(); k < out32; k += NT) c32[k] = k < 2 * S ? R[k] : 0u;
 }
 
-// Staged top level (Toom-3 or Toom-4), evaluation: word idx of the point
-// operands of a batch (layout ((NP i + e) * 2 + x) * S1 + w, NP points per
-// item) from the items' operands in HBM, masked to n bits, zero beyond,
-// split in parts of m words.
+// Staged top level (Toom-3 or Toom-4), evaluation of one item by one
+// workgroup: both operands are staged in LDS (masked to n bits, zero padded
+// to S words, smem holds 2S words), then the NP point operand pairs are
+// written to dst as ((e * 2 + x) * S1 + w), coalesced.
 template <class Top>
-__device__ __forceinline__ u32 staged_eval_word(const DevItem *items, const uint64_t *a_base, const uint64_t *b_base,
-                                                size_t idx) {
-    constexpr int S1 = Top::S1, m = Top::m, NP = Top::NP;
-    const u32 i = (u32)(idx / (2 * NP * S1));
-    const int r = (int)(idx - (size_t)i * 2 * NP * S1);
-    const int e = r / (2 * S1);
-    const int x = (r - e * 2 * S1) / S1;
-    const int w = r - e * 2 * S1 - x * S1;
-    const DevItem it = items[i];
-    const u32 *src = reinterpret_cast<const u32 *>(x ? b_base + it.b_off : a_base + it.a_off);
-    const int w32 = (int)((it.n + 31u) / 32u);
-    const u32 s = it.n % 32u;
-    const u32 top = s ? ((1u << s) - 1u) : 0xFFFFFFFFu;
-    auto part = [&](int, int p, int j) -> u32 {
-        if (j < 0 || j >= m) return 0u;
-        const int k = p * m + j;
-        if (k >= w32) return 0u;
-        const u32 v = src[k];
-        return k == w32 - 1 ? (v & top) : v;
-    };
-    return Top::point_word(e, x, w, part);
+__device__ __forceinline__ void staged_eval_item(const DevItem &it, const uint64_t *a_base, const uint64_t *b_base,
+                                                 u32 *dst, u32 *smem) {
+    constexpr int S1 = Top::S1, m = Top::m, S = Top::S, PER = 2 * Top::NP * S1;
+    stage<S>(a_base + it.a_off, b_base + it.b_off, it.n, smem);
+    __syncthreads();
+    auto part = [&](int x, int p, int j) -> u32 { return (j >= 0 && j < m) ? smem[x * S + p * m + j] : 0u; };
+    for (int idx = tid(); idx < PER; idx += NT) {
+        const int e = idx / (2 * S1);
+        const int r = idx - e * 2 * S1;
+        const int x = r >= S1 ? 1 : 0;
+        dst[idx] = Top::point_word(e, x, r - x * S1, part);
+    }
+    __syncthreads();  // smem is reused by the next item
 }
 
 // Staged top level, interpolation of one item from its NP point products

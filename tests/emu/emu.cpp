@@ -178,6 +178,23 @@ struct InterpJob {
     uint32_t *smem;
     unsigned tid;
 };
+struct EvalJob {
+    int which;
+    gf2x::DevItem it;
+    const uint64_t *a, *b;
+    uint32_t *dst;
+    uint32_t *smem;
+    unsigned tid;
+};
+void *eval_worker(void *p) {
+    EvalJob *j = static_cast<EvalJob *>(p);
+    threadIdx.x = j->tid;
+    int k = 0;
+#define EMU_EVAL_ITEM(id, name, T, cid, C) \
+    if (k++ == j->which) gf2x::staged_eval_item<gf2x::T>(j->it, j->a, j->b, j->dst, j->smem);
+    GF2X_STAGED_LIST(EMU_EVAL_ITEM)
+    return nullptr;
+}
 void *interp_worker(void *p) {
     InterpJob *j = static_cast<InterpJob *>(p);
     threadIdx.x = j->tid;
@@ -198,12 +215,22 @@ extern "C" int emu_staged(int which, const uint64_t *a, const uint64_t *b, uint6
     (void)m;
     gf2x::DevItem it{n, kind, 0u, 0u, 0, 0, 0};
     std::vector<uint32_t> ws_in(2 * (size_t)np * S1), ws_out(2 * (size_t)np * S1);
-    k = 0;
-    for (size_t idx = 0; idx < ws_in.size(); ++idx) {
-        int kk = 0;
-#define EMU_EVAL(id, name, T, cc, C) \
-        if (kk++ == which) ws_in[idx] = gf2x::staged_eval_word<gf2x::T>(&it, a, b, idx);
-        GF2X_STAGED_LIST(EMU_EVAL)
+    {
+        int S = 0;
+        k = 0;
+#define EMU_STAGED_S2(id, name, T, cc, C) \
+        if (k++ == which) S = gf2x::T::S;
+        GF2X_STAGED_LIST(EMU_STAGED_S2)
+        std::vector<uint32_t> esmem(2 * (size_t)S);
+        pthread_barrier_init(&g_bar, nullptr, gf2x::NT);
+        std::vector<pthread_t> th(gf2x::NT);
+        std::vector<EvalJob> jobs(gf2x::NT);
+        for (int t = 0; t < gf2x::NT; ++t) {
+            jobs[t] = EvalJob{which, it, a, b, ws_in.data(), esmem.data(), (unsigned)t};
+            pthread_create(&th[t], nullptr, eval_worker, &jobs[t]);
+        }
+        for (int t = 0; t < gf2x::NT; ++t) pthread_join(th[t], nullptr);
+        pthread_barrier_destroy(&g_bar);
     }
     for (int e = 0; e < np; ++e) {
         const uint64_t *pa = reinterpret_cast<const uint64_t *>(ws_in.data() + (size_t)e * 2 * S1);
