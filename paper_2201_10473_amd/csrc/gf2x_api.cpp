@@ -63,21 +63,46 @@ void default_table(gf2x_ctx *ctx) {
     for (uint32_t w = 0; w <= kMaxWords32; ++w) ctx->cls_of_w32[w] = default_class(w);
 }
 
-// Tuner cache: text lines "w32 class_name" override the default per size.
+// The direct class of each size: the one measured fastest by the tuner when
+// the table has it, else the direct form of the batch schedule.
+void direct_table(gf2x_ctx *ctx) {
+    for (uint32_t w = 0; w <= kMaxWords32; ++w) {
+        auto it = ctx->tuned_direct.find(w);
+        ctx->direct_of_w32[w] = it != ctx->tuned_direct.end() ? it->second : class_info(ctx->cls_of_w32[w]).direct;
+    }
+}
+
+int upload_direct_table(gf2x_ctx *ctx) {
+    uint8_t tab[kMaxWords32 + 1];
+    for (uint32_t w = 0; w <= kMaxWords32; ++w) tab[w] = (uint8_t)ctx->direct_of_w32[w];
+    if (!ctx->d_cls) {
+        HIP_TRY(hipMalloc(&ctx->d_cls, sizeof tab));
+        ctx->allocated += sizeof tab;
+    }
+    HIP_TRY(hipMemcpy(ctx->d_cls, tab, sizeof tab, hipMemcpyHostToDevice));
+    return GF2X_OK;
+}
+
+// Tuner cache: text lines "w32 class_name [direct_class_name]" override the
+// default per size; the optional third column is the fastest direct class.
 int load_tune_cache(gf2x_ctx *ctx, const char *path) {
     FILE *f = std::fopen(path, "r");
     if (!f) return GF2X_OK;  // no cache yet: defaults
-    char line[256];
+    char line[384];
     while (std::fgets(line, sizeof line, f)) {
         unsigned w = 0;
-        char name[128];
-        if (line[0] == '#' || std::sscanf(line, "%u %127s", &w, name) != 2) continue;
-        if (w == 0 || w > kMaxWords32) continue;
-        for (int c = 0; c < kNumClasses; ++c)
-            if (std::strcmp(class_info(c).name, name) == 0 && (uint32_t)class_info(c).S >= w) {
+        char name[128], dname[128];
+        if (line[0] == '#') continue;
+        const int got = std::sscanf(line, "%u %127s %127s", &w, name, dname);
+        if (got < 2 || w == 0 || w > kMaxWords32) continue;
+        for (int c = 0; c < kNumClasses; ++c) {
+            if ((uint32_t)class_info(c).S < w) continue;
+            if (std::strcmp(class_info(c).name, name) == 0) {
                 ctx->cls_of_w32[w] = c;
                 ctx->tuned[w] = c;
             }
+            if (got == 3 && c < kNumDirect && std::strcmp(class_info(c).name, dname) == 0) ctx->tuned_direct[w] = c;
+        }
     }
     std::fclose(f);
     return GF2X_OK;
@@ -282,15 +307,12 @@ int gf2x_create(gf2x_ctx **out, const gf2x_opts *opts) {
     ctx->num_cu = prop.multiProcessorCount;
     default_table(ctx);
     if (o.tune_cache) load_tune_cache(ctx, o.tune_cache);
-    uint8_t tab[kMaxWords32 + 1];
-    for (uint32_t w = 0; w <= kMaxWords32; ++w) tab[w] = (uint8_t)class_info(ctx->cls_of_w32[w]).direct;
-    e = hipMalloc(&ctx->d_cls, sizeof tab);
-    if (e == hipSuccess) e = hipMemcpy(ctx->d_cls, tab, sizeof tab, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
+    direct_table(ctx);
+    const int rc = upload_direct_table(ctx);
+    if (rc) {
         gf2x_destroy(ctx);
-        return device_error(e);
+        return rc;
     }
-    ctx->allocated += sizeof tab;
     *out = ctx;
     return GF2X_OK;
 }
@@ -321,7 +343,7 @@ int gf2x_mul(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b, u
     int rc = check_single(ctx, c, a, b, n_bits, 2 * words64(n_bits));
     if (rc) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
-    const int cls = class_info(ctx->cls_of_w32[(n_bits + 31u) / 32u]).direct;
+    const int cls = ctx->direct_of_w32[(n_bits + 31u) / 32u];
     HIP_TRY(launch_single(cls, a, b, c, n_bits, kKindFull, reinterpret_cast<hipStream_t>(stream)));
     return GF2X_OK;
 }
@@ -331,7 +353,7 @@ int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_
     int rc = check_single(ctx, c, a, b, n_bits, words64(n_bits));
     if (rc) return rc;
     HIP_TRY(hipSetDevice(ctx->device));
-    const int cls = class_info(ctx->cls_of_w32[(n_bits + 31u) / 32u]).direct;
+    const int cls = ctx->direct_of_w32[(n_bits + 31u) / 32u];
     HIP_TRY(launch_single(cls, a, b, c, n_bits, kKindCyclic, reinterpret_cast<hipStream_t>(stream)));
     return GF2X_OK;
 }
@@ -484,8 +506,8 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
             const uint64_t Wn = words64(n);
             for (uint32_t k = 0; k < batch; ++k) host[k] = DevItem{n, kKindCyclic, 0u, 0u, k * Wn, k * Wn, k * Wn};
             e = hipMemcpyAsync(d_items, host.data(), batch * sizeof(DevItem), hipMemcpyHostToDevice, s);
-            int best = -1;
-            float best_ms = 0.f;
+            int best = -1, best_direct = -1;
+            float best_ms = 0.f, best_direct_ms = 0.f;
             for (int c = 0; e == hipSuccess && c < kNumClasses; ++c) {
                 const ClassInfo &ci = class_info(c);
                 if ((uint32_t)ci.S < w32 || (double)ci.S > 1.6 * w32 + 8) continue;
@@ -506,29 +528,34 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
                     best = c;
                     best_ms = t;
                 }
+                if (e == hipSuccess && ci.child < 0 && (best_direct < 0 || t < best_direct_ms)) {
+                    best_direct = c;
+                    best_direct_ms = t;
+                }
             }
             if (e == hipSuccess && best >= 0) {
                 ctx->cls_of_w32[w32] = best;
                 ctx->tuned[w32] = best;
             }
+            if (e == hipSuccess && best_direct >= 0) ctx->tuned_direct[w32] = best_direct;
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e == hipSuccess) {
-            uint8_t tab[kMaxWords32 + 1];
-            for (uint32_t w = 0; w <= kMaxWords32; ++w) tab[w] = (uint8_t)class_info(ctx->cls_of_w32[w]).direct;
-            e = hipMemcpy(ctx->d_cls, tab, sizeof tab, hipMemcpyHostToDevice);
-        }
+        if (e == hipSuccess) direct_table(ctx);
         if (e0) hipEventDestroy(e0);
         if (e1) hipEventDestroy(e1);
         if (s) hipStreamDestroy(s);
         hipFree(buf);
         if (e != hipSuccess) return device_error(e);
+        const int rc = upload_direct_table(ctx);
+        if (rc) return rc;
     }
     if (out_path) {
         FILE *f = std::fopen(out_path, "w");
         if (!f) return GF2X_EINVAL;
-        std::fprintf(f, "# gf2x schedule table: <ceil(n/32)> <class name>, written by gf2x_tune\n");
-        for (auto &kv : ctx->tuned) std::fprintf(f, "%u %s\n", kv.first, class_info(kv.second).name);
+        std::fprintf(f, "# gf2x schedule table: <ceil(n/32)> <batch class> <fastest direct class>, written by gf2x_tune\n");
+        for (auto &kv : ctx->tuned)
+            std::fprintf(f, "%u %s %s\n", kv.first, class_info(kv.second).name,
+                         class_info(ctx->direct_of_w32[kv.first]).name);
         std::fclose(f);
     }
     return GF2X_OK;

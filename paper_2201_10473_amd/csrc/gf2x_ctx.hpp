@@ -29,8 +29,10 @@ struct gf2x_ctx {
     int num_cu = 0;
     size_t budget = 0;
     size_t allocated = 0;
-    int cls_of_w32[gf2x::kMaxWords32 + 1];
-    uint8_t *d_cls = nullptr;      // device copy of cls_of_w32
+    int cls_of_w32[gf2x::kMaxWords32 + 1];     // batch schedule per size (direct or staged)
+    int direct_of_w32[gf2x::kMaxWords32 + 1];  // best direct class per size (single products,
+                                               // device-resident items, serving)
+    uint8_t *d_cls = nullptr;                  // device copy of direct_of_w32
     gf2x::DevItem *d_items = nullptr;    // workspace for host item descriptors
     size_t d_items_cap = 0;
     hipEvent_t ws_free = nullptr;  // recorded after the last launch reading d_items / staged_ws
@@ -41,7 +43,8 @@ struct gf2x_ctx {
              gf2x::GraphEntry>
         graphs;
     gf2x::toeplitz::Workspace tz;
-    std::map<uint32_t, int> tuned;  // w32 -> class chosen by gf2x_tune or the cache file
+    std::map<uint32_t, int> tuned;         // w32 -> class chosen by gf2x_tune or the cache file
+    std::map<uint32_t, int> tuned_direct;  // w32 -> fastest direct class measured for that size
     // internal streams (default priority) for concurrent per-class launches,
     // forked from and joined back to the caller's stream with events
     static constexpr int kForks = 4;

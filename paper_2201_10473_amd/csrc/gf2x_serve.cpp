@@ -180,7 +180,7 @@ bool launch(gf2x_srv *srv) {
     for (uint32_t i = 0; i < count; ++i) {
         const Request &r = sl->reqs[i];
         const uint64_t W = (r.n + 63u) / 64u;
-        const int cls = class_info(srv->ctx->cls_of_w32[(r.n + 31u) / 32u]).direct;
+        const int cls = srv->ctx->direct_of_w32[(r.n + 31u) / 32u];
         tmp[i] = DevItem{r.n, kKindCyclic, (uint32_t)cls, 0u, off, off, off};
         sl->c_off[i] = off;
         off += W;
@@ -324,6 +324,18 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.host), srv->slot_bytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.dev), srv->slot_bytes);
     }
+    // Touch every page of the slot buffers once, host pages on the CPU and
+    // then one copy each way: the first use of fresh pinned and device pages
+    // is slower than later uses and would otherwise land on the requests of
+    // the first large batches.
+    for (Slot &sl : srv->slots) {
+        if (e != hipSuccess) break;
+        std::memset(sl.host, 0, srv->slot_bytes);
+        e = hipMemcpyAsync(sl.dev, sl.host, srv->slot_bytes, hipMemcpyHostToDevice, sl.stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(sl.host, sl.dev, srv->slot_bytes, hipMemcpyDeviceToHost, sl.stream);
+    }
+    for (Slot &sl : srv->slots)
+        if (e == hipSuccess) e = hipStreamSynchronize(sl.stream);
     if (e != hipSuccess) {
         gf2x_srv_destroy(srv);
         return e == hipErrorOutOfMemory ? GF2X_ENOMEM : GF2X_EDEVICE;

@@ -39,24 +39,40 @@ def make_requests(count, seed, sizes=inputs.RING_SIZES):
     return ns, off, A, B
 
 
-def warm_up(srv, seed):
-    """A few requests of every size through the server before the timed run
-    (loads every kernel the workload uses); not part of the measurement."""
+def warm_up(srv, seed, requests=None, rate=0.0, count=0):
+    """Before the timed run, and not part of the measurement: a few requests
+    of every size through the server (loads every kernel the workload uses),
+    then a replay of the first `count` timed requests at `rate`.  The first
+    replay in a process runs slower for its first tens of milliseconds (its
+    p99 is several ms higher); the timed replay measures the steady state."""
     ns, off, A, B = make_requests(6 * 8, seed, sizes=inputs.RING_SIZES)
     C = np.zeros_like(A)
     srv.submit(ns, A, off, B, off, C, off)
     srv.drain()
+    if requests is not None and rate > 0 and count > 0:
+        rns, rA, roff, rB, rC = requests
+        k = min(count, len(rns))
+        gaps = np.random.default_rng(seed).exponential(1.0 / rate, k)
+        arrival = (srv.now_ns() + int(0.005 * 1e9) + np.cumsum(gaps) * 1e9).astype(np.uint64)
+        srv.submit(rns[:k], rA, roff[:k], rB, roff[:k], rC, roff[:k], arrival)
+        srv.drain()
 
 
-def run(ctx, rate, count, seed, hbm_budget_bytes=0, streams=0, start_delay_s=0.01, warm=True, max_batch=0):
+def run(ctx, rate, count, seed, hbm_budget_bytes=0, streams=0, start_delay_s=0.01, warm=True, max_batch=0,
+        warm_requests=None):
     """Replay a Poisson process of `count` requests at `rate` per second."""
     ns, off, A, B = make_requests(count, seed)
-    C = np.zeros_like(A)
+    # write every page of the result buffer now: fresh zero pages are mapped
+    # on first write, which would otherwise be timed inside the first batches
+    C = np.empty_like(A)
+    C.fill(0)
     rng = np.random.default_rng(seed + 1)
     gaps = rng.exponential(1.0 / rate, count)
     with gf2x.Server(ctx, hbm_budget_bytes=hbm_budget_bytes, streams=streams, max_batch=max_batch) as srv:
         if warm:
-            warm_up(srv, seed + 2)
+            # warm-up replay: 0.1 s of traffic at the same rate (at least 2000 requests)
+            k = warm_requests if warm_requests is not None else max(2000, int(rate * 0.1))
+            warm_up(srv, seed + 2, (ns, A, off, B, C), rate, k)
             base = srv.stats()
         else:
             base = None
