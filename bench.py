@@ -209,7 +209,24 @@ def single_latency(ctx, n, calls, warmup, seed):
         raise AssertionError("single product at n=%d differs from the oracle" % n)
     return {"n": n, "calls": calls, "median_device_us": round(1e3 * float(np.median(dev)), 2),
             "median_host_us": round(1e6 * float(np.median(host)), 2),
-            "schedule": ctx.schedule_info(n)[3]}
+            "schedule": single_schedule(n)}
+
+
+def single_schedule(n):
+    """The class a single product of n bits runs in: the fourth column of the
+    packaged schedule table (the lowest single-product latency measured), else
+    the direct class of the third column, else the batch class."""
+    from paper_2201_10473_amd import gf2x
+
+    w = (n + 31) // 32
+    try:
+        for line in open(gf2x.DEFAULT_TUNE_CACHE):
+            f = line.split()
+            if f and not line.startswith("#") and int(f[0]) == w and len(f) >= 2:
+                return f[min(len(f), 4) - 1]
+    except (OSError, ValueError):
+        pass
+    return None
 
 
 def check_sample(res, n, count, k=6):

@@ -64,11 +64,15 @@ void default_table(gf2x_ctx *ctx) {
 }
 
 // The direct class of each size: the one measured fastest by the tuner when
-// the table has it, else the direct form of the batch schedule.
+// the table has it, else the direct form of the batch schedule.  The class
+// of a single product: the one with the lowest measured latency, else the
+// direct class.
 void direct_table(gf2x_ctx *ctx) {
     for (uint32_t w = 0; w <= kMaxWords32; ++w) {
         auto it = ctx->tuned_direct.find(w);
         ctx->direct_of_w32[w] = it != ctx->tuned_direct.end() ? it->second : class_info(ctx->cls_of_w32[w]).direct;
+        auto is = ctx->tuned_single.find(w);
+        ctx->single_of_w32[w] = is != ctx->tuned_single.end() ? is->second : ctx->direct_of_w32[w];
     }
 }
 
@@ -83,17 +87,18 @@ int upload_direct_table(gf2x_ctx *ctx) {
     return GF2X_OK;
 }
 
-// Tuner cache: text lines "w32 class_name [direct_class_name]" override the
-// default per size; the optional third column is the fastest direct class.
+// Tuner cache: text lines "w32 batch_class [direct_class [single_class]]"
+// override the default per size: the batch schedule, the fastest direct
+// class, and the class with the lowest single-product latency.
 int load_tune_cache(gf2x_ctx *ctx, const char *path) {
     FILE *f = std::fopen(path, "r");
     if (!f) return GF2X_OK;  // no cache yet: defaults
-    char line[384];
+    char line[512];
     while (std::fgets(line, sizeof line, f)) {
         unsigned w = 0;
-        char name[128], dname[128];
+        char name[128], dname[128], sname[128];
         if (line[0] == '#') continue;
-        const int got = std::sscanf(line, "%u %127s %127s", &w, name, dname);
+        const int got = std::sscanf(line, "%u %127s %127s %127s", &w, name, dname, sname);
         if (got < 2 || w == 0 || w > kMaxWords32) continue;
         for (int c = 0; c < kNumClasses; ++c) {
             if ((uint32_t)class_info(c).S < w) continue;
@@ -101,7 +106,8 @@ int load_tune_cache(gf2x_ctx *ctx, const char *path) {
                 ctx->cls_of_w32[w] = c;
                 ctx->tuned[w] = c;
             }
-            if (got == 3 && c < kNumDirect && std::strcmp(class_info(c).name, dname) == 0) ctx->tuned_direct[w] = c;
+            if (got >= 3 && c < kNumDirect && std::strcmp(class_info(c).name, dname) == 0) ctx->tuned_direct[w] = c;
+            if (got >= 4 && std::strcmp(class_info(c).name, sname) == 0) ctx->tuned_single[w] = c;
         }
     }
     std::fclose(f);
@@ -262,6 +268,57 @@ int launch_groups(gf2x_ctx *ctx, const DevItem *d_items, const std::vector<Group
     return GF2X_OK;
 }
 
+constexpr size_t kSingleChunk = 256;       // descriptors per device chunk
+constexpr size_t kMaxSingleItems = 4096;  // distinct (n, kind) kept on the device
+
+// One product: a direct class runs in one workgroup; a staged class spreads
+// it over the workgroups of its point products (lower latency for large n),
+// through the same descriptor and workspace path as a batch of one.
+int single_product(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b, uint32_t n_bits,
+                   uint32_t kind, hipStream_t s, int force_cls = -1) {
+    HIP_TRY(hipSetDevice(ctx->device));
+    const int cls = force_cls >= 0 ? force_cls : ctx->single_of_w32[(n_bits + 31u) / 32u];
+    if (class_info(cls).child < 0) {
+        HIP_TRY(launch_single(cls, a, b, c, n_bits, kind, s));
+        return GF2X_OK;
+    }
+    // the descriptor of (n, kind) lives on the device once written: no copy per call
+    DevItem *d_item = nullptr;
+    auto found = ctx->single_items.find({n_bits, kind});
+    if (found != ctx->single_items.end()) {
+        d_item = found->second;
+    } else if (ctx->single_items.size() < kMaxSingleItems) {
+        if (ctx->single_chunks.empty() || ctx->single_used == kSingleChunk) {
+            if (ctx->allocated + kSingleChunk * sizeof(DevItem) > ctx->budget) return GF2X_ENOMEM;
+            DevItem *chunk = nullptr;
+            HIP_TRY(hipMalloc(&chunk, kSingleChunk * sizeof(DevItem)));
+            ctx->allocated += kSingleChunk * sizeof(DevItem);
+            ctx->single_chunks.push_back(chunk);
+            ctx->single_used = 0;
+        }
+        d_item = ctx->single_chunks.back() + ctx->single_used;
+        const DevItem item{n_bits, kind, (uint32_t)cls, 0u, 0u, 0u, 0u};
+        HIP_TRY(hipMemcpy(d_item, &item, sizeof item, hipMemcpyHostToDevice));
+        ++ctx->single_used;
+        ctx->single_items[{n_bits, kind}] = d_item;
+    } else {  // table full: one workgroup
+        HIP_TRY(launch_single(class_info(cls).direct, a, b, c, n_bits, kind, s));
+        return GF2X_OK;
+    }
+    const size_t need = (staged_workspace_bytes(cls, 1) + 255) / 256 * 256;
+    int rc = ensure_ws(ctx, ctx->staged_ws, ctx->staged_ws_bytes, need, ctx->ws_free, ctx->ws_used);
+    if (rc == GF2X_ENOMEM) {  // no room for the workspace within the budget: one workgroup
+        HIP_TRY(launch_single(class_info(cls).direct, a, b, c, n_bits, kind, s));
+        return GF2X_OK;
+    }
+    if (rc) return rc;
+    if (ctx->ws_used) HIP_TRY(hipStreamWaitEvent(s, ctx->ws_free, 0));
+    HIP_TRY(launch_staged(cls, d_item, 1, c, a, b, ctx->staged_ws, ctx->num_cu, s));
+    HIP_TRY(hipEventRecord(ctx->ws_free, s));
+    ctx->ws_used = true;
+    return GF2X_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -333,6 +390,7 @@ void gf2x_destroy(gf2x_ctx *ctx) {
     for (int i = 0; i <= gf2x_ctx::kForks; ++i)
         if (ctx->fork_event[i]) hipEventDestroy(ctx->fork_event[i]);
     if (ctx->d_items) hipFree(ctx->d_items);
+    for (gf2x::DevItem *chunk : ctx->single_chunks) hipFree(chunk);
     if (ctx->d_cls) hipFree(ctx->d_cls);
     if (ctx->ws_free) hipEventDestroy(ctx->ws_free);
     delete ctx;
@@ -342,20 +400,14 @@ int gf2x_mul(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b, u
              gf2x_stream_t stream) {
     int rc = check_single(ctx, c, a, b, n_bits, 2 * words64(n_bits));
     if (rc) return rc;
-    HIP_TRY(hipSetDevice(ctx->device));
-    const int cls = ctx->direct_of_w32[(n_bits + 31u) / 32u];
-    HIP_TRY(launch_single(cls, a, b, c, n_bits, kKindFull, reinterpret_cast<hipStream_t>(stream)));
-    return GF2X_OK;
+    return single_product(ctx, c, a, b, n_bits, kKindFull, reinterpret_cast<hipStream_t>(stream));
 }
 
 int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b, uint32_t n_bits,
                     gf2x_stream_t stream) {
     int rc = check_single(ctx, c, a, b, n_bits, words64(n_bits));
     if (rc) return rc;
-    HIP_TRY(hipSetDevice(ctx->device));
-    const int cls = ctx->direct_of_w32[(n_bits + 31u) / 32u];
-    HIP_TRY(launch_single(cls, a, b, c, n_bits, kKindCyclic, reinterpret_cast<hipStream_t>(stream)));
-    return GF2X_OK;
+    return single_product(ctx, c, a, b, n_bits, kKindCyclic, reinterpret_cast<hipStream_t>(stream));
 }
 
 int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint64_t *c_base,
@@ -506,38 +558,59 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
             const uint64_t Wn = words64(n);
             for (uint32_t k = 0; k < batch; ++k) host[k] = DevItem{n, kKindCyclic, 0u, 0u, k * Wn, k * Wn, k * Wn};
             e = hipMemcpyAsync(d_items, host.data(), batch * sizeof(DevItem), hipMemcpyHostToDevice, s);
-            int best = -1, best_direct = -1;
-            float best_ms = 0.f, best_direct_ms = 0.f;
-            for (int c = 0; e == hipSuccess && c < kNumClasses; ++c) {
-                const ClassInfo &ci = class_info(c);
-                if ((uint32_t)ci.S < w32 || (double)ci.S > 1.6 * w32 + 8) continue;
-                float t = 0.f;
-                for (int rep = 0; e == hipSuccess && rep < 4; ++rep) {
-                    e = hipEventRecord(e0, s);
-                    if (e == hipSuccess) {
-                        if (ci.child >= 0) e = launch_staged(c, d_items, batch, C, A, B, staged_ws, ctx->num_cu, s);
-                        else e = launch_batched(c, d_items, batch, C, A, B, ctx->num_cu, s);
+            // Two passes over the candidates (so that no candidate is only
+            // measured while the clocks settle); per pass and candidate, one
+            // warm-up launch and three timed ones.  A class's batch time is
+            // its minimum over both passes, its single-product latency the
+            // median of its nine timed calls in the last pass.
+            float batch_ms[kNumClasses], single_ms[kNumClasses];
+            for (int c = 0; c < kNumClasses; ++c) batch_ms[c] = single_ms[c] = -1.f;
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int c = 0; e == hipSuccess && c < kNumClasses; ++c) {
+                    const ClassInfo &ci = class_info(c);
+                    if ((uint32_t)ci.S < w32 || (double)ci.S > 1.6 * w32 + 8) continue;
+                    for (int rep = 0; e == hipSuccess && rep < 4; ++rep) {
+                        e = hipEventRecord(e0, s);
+                        if (e == hipSuccess) {
+                            if (ci.child >= 0) e = launch_staged(c, d_items, batch, C, A, B, staged_ws, ctx->num_cu, s);
+                            else e = launch_batched(c, d_items, batch, C, A, B, ctx->num_cu, s);
+                        }
+                        if (e == hipSuccess) e = hipEventRecord(e1, s);
+                        if (e == hipSuccess) e = hipEventSynchronize(e1);
+                        float ms = 0.f;
+                        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                        if (e == hipSuccess && rep > 0 && (batch_ms[c] < 0 || ms < batch_ms[c])) batch_ms[c] = ms;
                     }
-                    if (e == hipSuccess) e = hipEventRecord(e1, s);
-                    if (e == hipSuccess) e = hipEventSynchronize(e1);
-                    float ms = 0.f;
-                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                    if (rep == 1 || (rep > 1 && ms < t)) t = ms;  // rep 0 is a warm-up
+                    if (pass == 0) continue;
+                    // latency of one product (item 0) through the entry point's
+                    // own path (descriptor, workspace, launches)
+                    float lat[10] = {};
+                    for (int rep = 0; e == hipSuccess && rep < 10; ++rep) {
+                        e = hipEventRecord(e0, s);
+                        if (e == hipSuccess && single_product(ctx, C, A, B, n, kKindCyclic, s, c) != GF2X_OK)
+                            e = hipErrorLaunchFailure;
+                        if (e == hipSuccess) e = hipEventRecord(e1, s);
+                        if (e == hipSuccess) e = hipEventSynchronize(e1);
+                        if (e == hipSuccess) e = hipEventElapsedTime(&lat[rep], e0, e1);
+                    }
+                    std::sort(lat + 1, lat + 10);
+                    single_ms[c] = lat[5];
                 }
-                if (e == hipSuccess && (best < 0 || t < best_ms)) {
-                    best = c;
-                    best_ms = t;
-                }
-                if (e == hipSuccess && ci.child < 0 && (best_direct < 0 || t < best_direct_ms)) {
+            }
+            int best = -1, best_direct = -1, best_single = -1;
+            for (int c = 0; c < kNumClasses; ++c) {
+                if (batch_ms[c] >= 0 && (best < 0 || batch_ms[c] < batch_ms[best])) best = c;
+                if (batch_ms[c] >= 0 && class_info(c).child < 0 &&
+                    (best_direct < 0 || batch_ms[c] < batch_ms[best_direct]))
                     best_direct = c;
-                    best_direct_ms = t;
-                }
+                if (single_ms[c] >= 0 && (best_single < 0 || single_ms[c] < single_ms[best_single])) best_single = c;
             }
             if (e == hipSuccess && best >= 0) {
                 ctx->cls_of_w32[w32] = best;
                 ctx->tuned[w32] = best;
             }
             if (e == hipSuccess && best_direct >= 0) ctx->tuned_direct[w32] = best_direct;
+            if (e == hipSuccess && best_single >= 0) ctx->tuned_single[w32] = best_single;
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e == hipSuccess) direct_table(ctx);
@@ -552,10 +625,12 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
     if (out_path) {
         FILE *f = std::fopen(out_path, "w");
         if (!f) return GF2X_EINVAL;
-        std::fprintf(f, "# gf2x schedule table: <ceil(n/32)> <batch class> <fastest direct class>, written by gf2x_tune\n");
+        std::fprintf(f,
+                     "# gf2x schedule table: <ceil(n/32)> <batch class> <fastest direct class> "
+                     "<lowest-latency class of one product>, written by gf2x_tune\n");
         for (auto &kv : ctx->tuned)
-            std::fprintf(f, "%u %s %s\n", kv.first, class_info(kv.second).name,
-                         class_info(ctx->direct_of_w32[kv.first]).name);
+            std::fprintf(f, "%u %s %s %s\n", kv.first, class_info(kv.second).name,
+                         class_info(ctx->direct_of_w32[kv.first]).name, class_info(ctx->single_of_w32[kv.first]).name);
         std::fclose(f);
     }
     return GF2X_OK;

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <vector>
 #include <tuple>
 
 #include "gf2x.h"
@@ -30,8 +31,10 @@ struct gf2x_ctx {
     size_t budget = 0;
     size_t allocated = 0;
     int cls_of_w32[gf2x::kMaxWords32 + 1];     // batch schedule per size (direct or staged)
-    int direct_of_w32[gf2x::kMaxWords32 + 1];  // best direct class per size (single products,
-                                               // device-resident items, serving)
+    int direct_of_w32[gf2x::kMaxWords32 + 1];  // best direct class per size (device-resident
+                                               // items, serving)
+    int single_of_w32[gf2x::kMaxWords32 + 1];  // lowest-latency class of one product (direct or
+                                               // staged)
     uint8_t *d_cls = nullptr;                  // device copy of direct_of_w32
     gf2x::DevItem *d_items = nullptr;    // workspace for host item descriptors
     size_t d_items_cap = 0;
@@ -45,6 +48,13 @@ struct gf2x_ctx {
     gf2x::toeplitz::Workspace tz;
     std::map<uint32_t, int> tuned;         // w32 -> class chosen by gf2x_tune or the cache file
     std::map<uint32_t, int> tuned_direct;  // w32 -> fastest direct class measured for that size
+    std::map<uint32_t, int> tuned_single;  // w32 -> lowest single-product latency measured
+    // Device descriptors of single products run in a staged class, one per
+    // (n, kind), written once and never overwritten (enqueued work may read
+    // them); grown in chunks.
+    std::map<std::pair<uint32_t, uint32_t>, gf2x::DevItem *> single_items;
+    std::vector<gf2x::DevItem *> single_chunks;
+    size_t single_used = 0;                // descriptors used in the last chunk
     // internal streams (default priority) for concurrent per-class launches,
     // forked from and joined back to the caller's stream with events
     static constexpr int kForks = 4;

@@ -118,11 +118,15 @@ ALL_CLASSES = [
 
 @pytest.mark.parametrize("name,S", ALL_CLASSES)
 def test_every_schedule_class(tmp_path, name, S):
-    """Force each class through a tuner table and check a full-size and a ragged n."""
+    """Force each class through a tuner table and check a full-size and a ragged n,
+    as single products (staged classes across several workgroups) and as a batch."""
     import torch
     ns = sorted({min(S * 32, gf2x.GF2X_MAX_BITS), max(1, min(S * 32, gf2x.GF2X_MAX_BITS) - 37)})
     table = tmp_path / "tune.txt"
-    table.write_text("".join("%d %s\n" % ((n + 31) // 32, name) for n in ns))
+    # the class serves batches and single products (a staged class then spreads
+    # one product over several workgroups); a staged name in the direct column
+    # is ignored, so device-resident items fall back to its direct form
+    table.write_text("".join("%d %s %s %s\n" % ((n + 31) // 32, name, name, name) for n in ns))
     with gf2x.Context(0, tune_cache=str(table)) as c:
         for n in ns:
             assert c.schedule_info(n)[3] == name
