@@ -58,6 +58,10 @@ struct Request {
 };
 
 constexpr int kSubStreams = 6;  // one per size class present in a batch
+// A batch of at most this many requests runs each product in the class with
+// the lowest single-product latency (a staged class spreads a product over
+// several workgroups); larger batches use the fastest direct classes.
+constexpr uint32_t kSmallBatch = 64;
 
 struct Slot {
     hipStream_t stream = nullptr;
@@ -66,6 +70,7 @@ struct Slot {
     hipEvent_t fork = nullptr, join[kSubStreams] = {};
     char *host = nullptr;   // pinned: [items | a | b | c]
     char *dev = nullptr;    // device: same layout
+    char *ws = nullptr;     // device workspace of the staged groups of a small batch
     std::vector<Request> reqs;
     std::vector<uint64_t> c_off;  // word offset of each request's result in the c region
     size_t c_region = 0;          // byte offset of the c region
@@ -79,6 +84,7 @@ struct gf2x_srv {
     gf2x_ctx *ctx = nullptr;
     uint32_t max_bits = 0, max_batch = 0, max_pending = 0;
     size_t slot_bytes = 0;
+    size_t ws_bytes = 0;  // per slot; 0 when the budget leaves no room
     std::vector<Slot> slots;
     std::mutex mu;
     std::condition_variable cv;
@@ -177,10 +183,12 @@ bool launch(gf2x_srv *srv) {
     std::vector<DevItem> tmp(count);
     sl->c_off.resize(count);
     uint64_t off = 0;
+    const bool small = count <= kSmallBatch && srv->ws_bytes > 0;
     for (uint32_t i = 0; i < count; ++i) {
         const Request &r = sl->reqs[i];
         const uint64_t W = (r.n + 63u) / 64u;
-        const int cls = srv->ctx->direct_of_w32[(r.n + 31u) / 32u];
+        const uint32_t w32 = (r.n + 31u) / 32u;
+        const int cls = small ? srv->ctx->single_of_w32[w32] : srv->ctx->direct_of_w32[w32];
         tmp[i] = DevItem{r.n, kKindCyclic, (uint32_t)cls, 0u, off, off, off};
         sl->c_off[i] = off;
         off += W;
@@ -217,13 +225,19 @@ bool launch(gf2x_srv *srv) {
     if (e == hipSuccess && fork) e = hipEventRecord(sl->fork, sl->stream);
     uint32_t first = 0;
     int g = 0;
+    char *wp = sl->ws;  // staged groups carve their workspace regions in order
     while (e == hipSuccess && first < count) {
         uint32_t last = first;
         while (last < count && tmp[last].cls == tmp[first].cls) ++last;
         hipStream_t sub = fork ? sl->sub[g % kSubStreams] : sl->stream;
         if (fork && g < kSubStreams) e = hipStreamWaitEvent(sub, sl->fork, 0);
-        if (e == hipSuccess)
-            e = launch_batched((int)tmp[first].cls, d_items + first, last - first, dc, da, db, srv->ctx->num_cu, sub);
+        const int cls = (int)tmp[first].cls;
+        if (e == hipSuccess && class_info(cls).child >= 0) {
+            e = launch_staged(cls, d_items + first, last - first, dc, da, db, wp, srv->ctx->num_cu, sub);
+            wp += round_up(staged_workspace_bytes(cls, last - first), 256);
+        } else if (e == hipSuccess) {
+            e = launch_batched(cls, d_items + first, last - first, dc, da, db, srv->ctx->num_cu, sub);
+        }
         {
             std::lock_guard<std::mutex> lk(srv->mu);
             srv->stats.launches++;
@@ -301,7 +315,14 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
     if (streams > 16 || max_bits > kMaxBits) return GF2X_EINVAL;
     const uint64_t Wmax = (max_bits + 63u) / 64u;
     const size_t per_req = sizeof(DevItem) + 3 * Wmax * 8;
-    uint64_t max_batch = budget / streams / per_req;
+    // workspace of the staged groups of a small batch: all of its requests in
+    // the staged class with the largest workspace, plus rounding per group
+    size_t ws_bytes = 0;
+    for (int c = 0; c < kNumClasses; ++c)
+        if (class_info(c).child >= 0) ws_bytes = std::max(ws_bytes, staged_workspace_bytes(c, kSmallBatch));
+    ws_bytes = round_up(ws_bytes + (size_t)kNumClasses * 1024, 256);
+    if (ws_bytes * streams * 2 > budget) ws_bytes = 0;  // keep most of the budget for the slots
+    uint64_t max_batch = (budget - ws_bytes * streams) / streams / per_req;
     if (o.max_batch && o.max_batch < max_batch) max_batch = o.max_batch;
     if (max_batch < 1) return GF2X_ENOMEM;  // the budget cannot hold one request per stream
     gf2x_srv *srv = new (std::nothrow) gf2x_srv();
@@ -311,6 +332,7 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
     srv->max_batch = (uint32_t)std::min<uint64_t>(max_batch, 1u << 20);
     srv->max_pending = o.max_pending ? o.max_pending : (1u << 22);
     srv->slot_bytes = round_up((size_t)srv->max_batch * sizeof(DevItem), 256) + 3 * (size_t)srv->max_batch * Wmax * 8;
+    srv->ws_bytes = ws_bytes;
     srv->slots.resize(streams);
     hipError_t e = hipSetDevice(ctx->device);
     for (Slot &sl : srv->slots) {
@@ -323,6 +345,7 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
         }
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.host), srv->slot_bytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.dev), srv->slot_bytes);
+        if (e == hipSuccess && srv->ws_bytes) e = hipMalloc(reinterpret_cast<void **>(&sl.ws), srv->ws_bytes);
     }
     // Touch every page of the slot buffers once, host pages on the CPU and
     // then one copy each way: the first use of fresh pinned and device pages
@@ -341,7 +364,7 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
         return e == hipErrorOutOfMemory ? GF2X_ENOMEM : GF2X_EDEVICE;
     }
     srv->stats.max_batch = srv->max_batch;
-    srv->stats.hbm_bytes = srv->slot_bytes * streams;
+    srv->stats.hbm_bytes = (srv->slot_bytes + srv->ws_bytes) * streams;
     srv->thread = std::thread(scheduler, srv);
     *out = srv;
     return GF2X_OK;
@@ -412,6 +435,7 @@ void gf2x_srv_destroy(gf2x_srv *srv) {
     for (Slot &sl : srv->slots) {
         if (sl.stream) hipStreamSynchronize(sl.stream);
         if (sl.dev) hipFree(sl.dev);
+        if (sl.ws) hipFree(sl.ws);
         if (sl.host) hipHostFree(sl.host);
         if (sl.done) hipEventDestroy(sl.done);
         if (sl.fork) hipEventDestroy(sl.fork);
