@@ -213,11 +213,13 @@ __device__ __forceinline__ u32 xor3(u32 a, u32 b, u32 c) { return __builtin_amdg
 // Splitting (KaratRec, Appendix A): a node of SL words with operands [a | b]
 // becomes three children of H = SL/2 words, in this order:
 //   child 0: (a0, b0), child 1: (a1, b1), child 2: (a0 + a1, b0 + b1).
-// Every level is stored densely: node v's operands at v*2*SL.  Column
-// r = x*H + w of node v is word w of operand x of each child.
-template <int NL, int SL>
+// Node v's operands are at v*2*SL; the children are written at a stride of
+// CS >= 2H words (CS > 2H pads a level).  Column r = x*H + w of node v is
+// word w of operand x of each child.
+template <int NL, int SL, int CS = SL>
 __device__ __forceinline__ void k2_split(const u32 *src, u32 *dst) {
     constexpr int H = SL / 2;
+    static_assert(CS >= 2 * H, "child stride holds a child");
     grid_map2<NL, 2 * H, 2>(
         [&](int v, int r, u32 (&x)[2]) {
             const u32 *s = src + v * 2 * SL + r + (r >= H ? H : 0);  // word w of operand x: x*SL + w
@@ -225,15 +227,15 @@ __device__ __forceinline__ void k2_split(const u32 *src, u32 *dst) {
             x[1] = s[H];
         },
         [&](int v, int r, const u32 (&x)[2]) {
-            u32 *d = dst + 3 * v * 2 * H + r;
+            u32 *d = dst + 3 * v * CS + r;
             d[0] = x[0];
-            d[2 * H] = x[1];
-            d[4 * H] = x[0] ^ x[1];
+            d[CS] = x[1];
+            d[2 * CS] = x[0] ^ x[1];
         });
 }
 
 // The root split, reading the root operands from a source.
-template <int SL, class Src>
+template <int SL, class Src, int CS = SL>
 __device__ __forceinline__ void k2_split_src(const Src &src, u32 *dst) {
     constexpr int H = SL / 2;
     grid_map<1, 2 * H>([&](int, int r) {
@@ -242,24 +244,25 @@ __device__ __forceinline__ void k2_split_src(const Src &src, u32 *dst) {
         const u32 lo = src.get(x, w);
         const u32 hi = src.get(x, H + w);
         dst[r] = lo;
-        dst[2 * H + r] = hi;
-        dst[4 * H + r] = lo ^ hi;
+        dst[CS + r] = hi;
+        dst[2 * CS + r] = lo ^ hi;
     });
 }
 
 // Reconstruction (KaratRec): R = R0 + (R0 + R1 + R2) X^{32H} + R1 X^{64H}
-// with children products R_k of 2H words stored densely; since R0 and R1 are
-// adjacent, [R0 | R1] already is R0 + R1 X^{64H}.  Parent products are 4H
-// words, stored densely.  Column j < 2H of node v writes the middle word
-// H + j and one outer word: word j (= R0[j]) when j < H, else word 2H + j
-// (= R1[j]).
-template <int NL, int H>
+// with children products R_k of 2H words at a stride of CS words.  Parent
+// products are 4H words, stored densely.  Column j < 2H of node v writes the
+// middle word H + j (R0[H + j] or R1[j - H], plus R0[j] + R1[j] + R2[j]) and
+// one outer word: word j (= R0[j]) when j < H, else word 2H + j (= R1[j]).
+template <int NL, int H, int CS = 2 * H>
 __device__ __forceinline__ void k2_merge(const u32 *src, u32 *dst) {
+    static_assert(CS >= 2 * H, "child stride holds a child");
     grid_map2<NL, 2 * H, 2>(
         [&](int v, int j, u32 (&x)[2]) {
-            const u32 *R = src + 3 * v * 2 * H + j;
-            const u32 r0 = R[0], r1 = R[2 * H];
-            x[0] = xor3(R[H], r0, r1) ^ R[4 * H];
+            const u32 *R = src + 3 * v * CS + j;
+            const u32 r0 = R[0], r1 = R[CS];
+            const u32 rm = j < H ? R[H] : R[CS - H];  // word H + j of [R0 | R1]
+            x[0] = xor3(rm, r0, r1) ^ R[2 * CS];
             x[1] = j < H ? r0 : r1;
         },
         [&](int v, int j, const u32 (&x)[2]) {
@@ -289,7 +292,11 @@ struct ParK2 {
     static constexpr bool IS_SEQ = false;
     static constexpr int S = T << D;
     static constexpr long long UNITS = pow3(D);
-    static constexpr int DA_WORDS = D >= 1 ? (int)(4 * T * pow3(D - 1)) : 2 * T;
+    // Level D-1 (the units' parents) is stored at a node stride of 4T + 1
+    // words: an odd stride spreads the nodes read and XORed by the lanes of a
+    // wave over distinct LDS banks.
+    static constexpr int NS = D >= 2 ? 4 * T + 1 : 4 * T;
+    static constexpr int DA_WORDS = D >= 1 ? (int)(NS * pow3(D - 1)) : 2 * T;
     static constexpr int DB_WORDS = D >= 2 ? (int)(8 * T * pow3(D - 2)) : 0;
     static constexpr int SCRATCH = DA_WORDS + DB_WORDS;
     static constexpr long long BASE = UNITS * T * T;   // 32x32 word products
@@ -309,7 +316,8 @@ struct ParK2 {
     template <int L>
     __device__ __forceinline__ static void down(u32 *DA, u32 *DB) {
         if constexpr (L + 1 <= D - 1) {
-            k2_split<(int)pow3(L), (T << (D - L))>(level_buf<L>(DA, DB), level_buf<L + 1>(DA, DB));
+            constexpr int CS = (L + 1 == D - 1) ? NS : (T << (D - L));
+            k2_split<(int)pow3(L), (T << (D - L)), CS>(level_buf<L>(DA, DB), level_buf<L + 1>(DA, DB));
             __syncthreads();
             down<L + 1>(DA, DB);
         }
@@ -321,7 +329,8 @@ struct ParK2 {
         if constexpr (L < 0) {
             return level_buf<0>(DA, DB);
         } else {
-            k2_merge<(int)pow3(L), (T << (D - L - 1))>(level_buf<L + 1>(DA, DB), level_buf<L>(DA, DB));
+            constexpr int CS = (L + 1 == D - 1) ? NS : (T << (D - L));
+            k2_merge<(int)pow3(L), (T << (D - L - 1)), CS>(level_buf<L + 1>(DA, DB), level_buf<L>(DA, DB));
             __syncthreads();
             return up<L - 1>(DA, DB);
         }
@@ -345,7 +354,7 @@ struct ParK2 {
                     blo = src.get(1, w);
                     bhi = src.get(1, T + w);
                 } else {
-                    const u32 *node = DA + v * 4 * T;  // [a_v (2T) | b_v (2T)]
+                    const u32 *node = DA + v * NS;  // [a_v (2T) | b_v (2T)]
                     alo = node[w];
                     ahi = node[T + w];
                     blo = node[2 * T + w];
@@ -360,7 +369,7 @@ struct ParK2 {
         __syncthreads();
         if (active) {
             unit_mul<T>(a, b, c);
-            u32 *q = DA + v * 4 * T + T * (k < 2 ? k : 1);
+            u32 *q = DA + v * NS + T * (k < 2 ? k : 1);
 #pragma unroll
             for (int w = 0; w < T; ++w) {
                 lds_xor(q + w, c[w]);
@@ -392,7 +401,7 @@ struct ParK2 {
             return DA;
         } else {
             if constexpr (D >= 2) {
-                k2_split_src<S>(src, level_buf<1>(DA, DB));
+                k2_split_src<S, Src, (D == 2 ? NS : S)>(src, level_buf<1>(DA, DB));
                 __syncthreads();
                 down<1>(DA, DB);
             }
@@ -793,36 +802,42 @@ struct TopT4 {
         auto A = [&](const u32 *c, int j) -> u32 { return (j >= 0 && j < L) ? c[j] : 0u; };
         auto s06 = [&](int j) -> u32 { return P(0, j) ^ P(6, j); };
         const int t = tid();
-        // u: (x E(x) + z E(z)) / x, then / (x^3 + 1)
+        // One pass over the point products: every term of the five
+        // numerators that depends on them alone (the terms in u, v, c1, c3
+        // are added once those are known).
         for (int k = t; k < L; k += NT) {
-            const int j = k + 1;
-            U[k] = P(2, j) ^ P(4, j) ^ P(3, j) ^ P(5, j) ^ s06(j) ^ s06(j - 2) ^ s06(j - 4);
+            const int j1 = k + 1, j2 = k + 2;
+            // (x E(x) + z E(z)) / x
+            U[k] = P(2, j1) ^ P(4, j1) ^ P(3, j1) ^ P(5, j1) ^ s06(j1) ^ s06(j1 - 2) ^ s06(j1 - 4);
+            // x E(x) / x^2, without the (x + x^5) u term
+            V[k] = P(2, j2) ^ P(4, j2) ^ s06(j2) ^ s06(j2 - 6);
+            // C(1) + c0 + c6, without u + v
+            C3[k] = P(1, k) ^ s06(k);
+            // (x G(x) + z G(z)) / x, without the c3, v, u terms
+            C1[k] = P(2, j1) ^ P(3, j1) ^ P(6, j1) ^ P(6, j1 - 2) ^ P(6, j1 - 4);
+            // x G(x) / x^2, without the c3, v, u, c1 terms
+            C2[k] = P(2, j2) ^ P(0, j2) ^ P(6, j2 - 6);
         }
         __syncthreads();
+        // u = ... / (x^3 + 1)
         scan_xor_stride<L, 3>(U, tmp);
-        // v: (x E(x) + (x + x^5) u) / x^2, then / (x^2 + 1)
-        for (int k = t; k < L; k += NT) {
-            const int j = k + 2;
-            V[k] = P(2, j) ^ P(4, j) ^ s06(j) ^ s06(j - 6) ^ A(U, j - 1) ^ A(U, j - 5);
-        }
+        // v = (x E(x) + (x + x^5) u) / x^2, then / (x^2 + 1)
+        for (int k = t; k < L; k += NT) V[k] ^= A(U, k + 1) ^ A(U, k - 3);
         __syncthreads();
         scan_xor_stride<L, 2>(V, tmp);
-        for (int k = t; k < L; k += NT) C3[k] = P(1, k) ^ s06(k) ^ U[k] ^ V[k];
+        // c3 = C(1) + c0 + c6 + u + v
+        for (int k = t; k < L; k += NT) C3[k] ^= U[k] ^ V[k];
         __syncthreads();
-        // c1: (x G(x) + z G(z)) / x, then / (x^3 + 1)
-        for (int k = t; k < L; k += NT) {
-            const int j = k + 1;
-            C1[k] = P(2, j) ^ P(3, j) ^ P(6, j) ^ P(6, j - 2) ^ P(6, j - 4) ^ A(C3, j) ^ A(C3, j - 1) ^ A(C3, j - 2) ^
-                    A(V, j) ^ A(U, j) ^ A(U, j - 1) ^ A(U, j - 4);
-        }
+        // c1 = (x G(x) + z G(z)) / x, then / (x^3 + 1):
+        // the terms (1 + x + x^2) c3 + v + (1 + x + x^4) u at word k + 1
+        for (int k = t; k < L; k += NT)
+            C1[k] ^= A(C3, k + 1) ^ A(C3, k) ^ A(C3, k - 1) ^ A(V, k + 1) ^ A(U, k + 1) ^ A(U, k) ^ A(U, k - 3);
         __syncthreads();
         scan_xor_stride<L, 3>(C1, tmp);
-        // c2: (x G(x) + (x + x^5) c1) / x^2, then / (x^2 + 1)
-        for (int k = t; k < L; k += NT) {
-            const int j = k + 2;
-            C2[k] = P(2, j) ^ P(0, j) ^ P(6, j - 6) ^ A(C3, j - 3) ^ A(V, j - 4) ^ A(U, j - 5) ^ A(C1, j - 1) ^
-                    A(C1, j - 5);
-        }
+        // c2 = (x G(x) + (x + x^5) c1) / x^2, then / (x^2 + 1):
+        // the terms x^3 c3 + x^4 v + x^5 u + (x + x^5) c1 at word k + 2
+        for (int k = t; k < L; k += NT)
+            C2[k] ^= A(C3, k - 1) ^ A(V, k - 2) ^ A(U, k - 3) ^ A(C1, k + 1) ^ A(C1, k - 3);
         __syncthreads();
         scan_xor_stride<L, 2>(C2, tmp);
         // recomposition: c0 + c1 Y + ... + c6 Y^6, c4 = v + c2, c5 = u + c1
