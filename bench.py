@@ -317,7 +317,8 @@ def main():
     ap.add_argument("--no-one-per-launch", action="store_true")
     ap.add_argument("--only-n", type=int, default=0, help="time only this ring size (profiling runs)")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-requests", type=int, default=20000)
+    ap.add_argument("--serving-requests", type=int, default=0,
+                    help="requests per serving rate (default: 0.5 s of traffic, 20000 to 100000)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -405,12 +406,16 @@ def main():
         if not args.no_serving:
             from paper_2201_10473_amd import serve
 
-            for rate in (10000, 100000, 500000):
-                log("serving: Poisson %d req/s" % rate)
-                res, bufs = serve.run(ctx, rate, args.serving_requests, inputs.SEED_BASE + 5)
-                serve.check_against_batched(ctx, *bufs)
-                serving.append(res)
-                log("  achieved %.0f req/s p50 %.1f us p99 %.1f us" % (res["achieved_rate"], res["p50_us"], res["p99_us"]))
+            # the server gets a context of its own, as a serving process would
+            with gf2x.Context(0) as sctx:
+                for rate in (10000, 100000, 500000):
+                    log("serving: Poisson %d req/s" % rate)
+                    count = args.serving_requests or min(100000, max(20000, int(rate * 0.5)))
+                    res, bufs = serve.run(sctx, rate, count, inputs.SEED_BASE + 5)
+                    serve.check_against_batched(sctx, *bufs)
+                    serving.append(res)
+                    log("  achieved %.0f req/s p50 %.1f us p99 %.1f us" % (res["achieved_rate"], res["p50_us"],
+                                                                           res["p99_us"]))
 
     head = sizes[0]
     main_res = results[head]
