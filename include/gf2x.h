@@ -99,13 +99,18 @@ void gf2x_destroy(gf2x_ctx *ctx);
 
 /* Full product c = a*b in F2[X] (Section 2.1).
  * a, b: W(n) words each; c: 2*W(n) words (bits >= 2n-1 written zero).
- * c must not overlap a or b.  Errors: GF2X_EINVAL, GF2X_EDEVICE. */
+ * c must not overlap a or b.  Errors: GF2X_EINVAL, GF2X_EDEVICE, GF2X_ENOMEM.
+ * The product runs in the class with the lowest measured single-product
+ * latency for its size: one workgroup, or a staged class spread over several
+ * workgroups (then the context's workspace is used, ordered by its event, and
+ * the first call for a given (n, kind) writes a small descriptor to the device
+ * synchronously).  On a stream under capture it is always one launch. */
 int gf2x_mul(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b,
              uint32_t n_bits, gf2x_stream_t stream);
 
 /* Ring product c = a*b mod (X^n - 1) (Section 1).  a, b, c: W(n) words each;
- * bits >= n of c written zero.  c must not overlap a or b.
- * Errors: GF2X_EINVAL, GF2X_EDEVICE. */
+ * bits >= n of c written zero.  c must not overlap a or b.  Scheduled as
+ * gf2x_mul.  Errors: GF2X_EINVAL, GF2X_EDEVICE, GF2X_ENOMEM. */
 int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b,
                     uint32_t n_bits, gf2x_stream_t stream);
 
@@ -142,11 +147,15 @@ int gf2x_schedule_info(gf2x_ctx *ctx, uint32_t n_bits, uint32_t *padded_words32,
 /* Autotuner.  For each n in sizes[0..nsizes), time every size class whose
  * padded size holds n (up to 1.6x padding) on a batch of `batch` ring
  * products of synthetic operands in a temporary device buffer (contents do
- * not matter: the kernels are constant time), keep the fastest class in the
- * context's table, and, if out_path is not NULL, write the context's tuned
- * choices to that file ("w32 class_name" lines, the format opts->tune_cache
- * reads).  This call is synchronous: it waits for the device on a private
- * stream.  Errors: GF2X_EINVAL, GF2X_ENOMEM, GF2X_EDEVICE. */
+ * not matter: the kernels are constant time), and the latency of one product
+ * through the gf2x_mul_cyclic path in each class.  The context's tables keep,
+ * per size, the fastest class for batches, the fastest direct (one workgroup
+ * per product) class, and the lowest-latency class for single products.  If
+ * out_path is not NULL the tuned sizes are written to that file, one line
+ * "w32 batch_class direct_class single_class" each, the format
+ * opts->tune_cache reads (lines with only the first one or two classes are
+ * accepted too).  This call is synchronous: it waits for the device on a
+ * private stream.  Errors: GF2X_EINVAL, GF2X_ENOMEM, GF2X_EDEVICE. */
 int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t batch, const char *out_path);
 
 /* ------------------------------------------------------------------ serving
@@ -157,8 +166,11 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
  * stay within hbm_budget_bytes.  Requests whose arrival time has passed are
  * admitted into free slots in submission order; while a slot's batch runs,
  * later arrivals form the next batch on another slot, so their work overlaps
- * on the device.  Results are identical to gf2x_mul_cyclic of the same
- * operands (the same kernels run them). */
+ * on the device.  A batch of at most 64 requests runs each product in its
+ * size's lowest-latency class (possibly staged, using a per-slot workspace
+ * that is part of the budget when the budget allows it); larger batches run
+ * one workgroup per product.  Results are identical to gf2x_mul_cyclic of the
+ * same operands (every class computes the same exact product). */
 typedef struct gf2x_srv gf2x_srv;
 
 typedef struct gf2x_srv_opts {

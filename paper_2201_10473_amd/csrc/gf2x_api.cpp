@@ -282,6 +282,15 @@ int single_product(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t
         HIP_TRY(launch_single(cls, a, b, c, n_bits, kind, s));
         return GF2X_OK;
     }
+    // Under stream capture the product stays one launch of the direct class:
+    // the staged path waits on the context's workspace event and may write a
+    // descriptor synchronously, neither of which belongs in a captured graph.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cap));
+    if (cap != hipStreamCaptureStatusNone) {
+        HIP_TRY(launch_single(class_info(cls).direct, a, b, c, n_bits, kind, s));
+        return GF2X_OK;
+    }
     // the descriptor of (n, kind) lives on the device once written: no copy per call
     DevItem *d_item = nullptr;
     auto found = ctx->single_items.find({n_bits, kind});

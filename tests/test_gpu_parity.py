@@ -189,6 +189,42 @@ def test_batched_graph_replays(ctx):
         assert np.array_equal(outs[0][i], oracle.mul_cyclic(A[i], B[i], n))
 
 
+def test_single_products_staged_and_captured(ctx):
+    """Single products at sizes whose lowest-latency class is staged (several
+    workgroups per product), eager and captured in a HIP graph (where the
+    product is one launch of the direct class); every replay, with eager work
+    in between, equals the oracle."""
+    import torch
+    for n in (17669, 57637):
+        W = oracle.words(n)
+        a = inputs.dense(n, SEED + 9, n, 0)
+        b = inputs.dense(n, SEED + 9, n, 1)
+        ref = oracle.mul_cyclic(a, b, n)
+        dA, dB, dC = to_dev(a), to_dev(b), empty_dev(W)
+        print("case single eager n=%d schedule %s" % (n, ctx.schedule_info(n)[3]), flush=True)
+        ctx.mul_cyclic(dC, dA, dB, n)
+        torch.cuda.synchronize()
+        assert np.array_equal(from_dev(dC), ref)
+        dG = empty_dev(W)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            ctx.mul_cyclic(dG, dA, dB, n)  # warm-up outside the capture
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        print("case single captured n=%d" % n, flush=True)
+        with torch.cuda.graph(g):
+            ctx.mul_cyclic(dG, dA, dB, n)
+        for rep in range(3):
+            dG.zero_()
+            ctx.mul_cyclic(dC, dB, dA, n)  # eager work between replays
+            g.replay()
+            torch.cuda.synchronize()
+            assert np.array_equal(from_dev(dG), ref), (n, rep)
+            assert np.array_equal(from_dev(dC), ref), (n, rep)
+
+
 def test_batched_device_items(ctx):
     import torch
     n = 35851
