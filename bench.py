@@ -286,6 +286,16 @@ def cpu_baseline(n, seed, target_s=12.0):
     }
 
 
+def kernel_sources():
+    """The files that define the batched kernels and their launch: the device
+    headers, the kernel translation units and the launchers (not the host API,
+    the server or the Toeplitz path), in name order."""
+    csrc = os.path.join(ROOT, "paper_2201_10473_amd", "csrc")
+    keep = ("gf2x_device.hpp", "gf2x_product.hpp", "gf2x_internal.hpp", "gf2x_launch.hpp", "gf2x_kern_direct.hpp",
+            "gf2x_kernels.hip")
+    return [os.path.join(csrc, f) for f in sorted(os.listdir(csrc)) if f in keep or f.startswith("gf2x_kern_")]
+
+
 def traffic_from_profile(kernel_key):
     """HBM bytes per launch measured with rocprofv3 --pmc (FETCH_SIZE, WRITE_SIZE),
     if a summary for the current kernel sources is committed under profiles/."""
@@ -299,9 +309,8 @@ def traffic_from_profile(kernel_key):
     except Exception:
         return None
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2201_10473_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        h.update(open(os.path.join(csrc, f), "rb").read())
+    for path in kernel_sources():
+        h.update(open(path, "rb").read())
     entry = data.get(kernel_key)
     if not entry or entry.get("sources_sha256") != h.hexdigest():
         return None
