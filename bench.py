@@ -229,6 +229,47 @@ def single_schedule(n):
     return None
 
 
+def time_inverse(ctx, n, seed, batch=1024, reps=10):
+    """gf2x_inv_cyclic_batched on odd-weight operands: median device time of
+    one inverse and of a batch; two results checked against the oracle."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2201_10473_amd import gf2x, inputs
+
+    W = gf2x.words(n)
+    A = inputs.dense_batch(n, batch, seed, 0)
+    A[:, -1] &= inputs.top_mask(n)
+    weight = np.count_nonzero(np.unpackbits(A.view(np.uint8), axis=1), axis=1)
+    A[:, 0] ^= (weight % 2 == 0).astype(np.uint64)  # odd weight: invertible for this n
+    out = {"n": n}
+    for count in (1, batch):
+        off = np.arange(count, dtype=np.uint64) * W
+        items = gf2x.make_items(n, gf2x.KIND_CYCLIC, off, off, off)
+        dA = torch.from_numpy(A[:count].ravel().view(np.int64)).cuda()
+        dC = torch.zeros(count * W, dtype=torch.int64, device="cuda")
+        for _ in range(3):
+            ctx.inv_cyclic_batched(items, dC, dA)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record()
+            ctx.inv_cyclic_batched(items, dC, dA)
+            e.record()
+            e.synchronize()
+            ts.append(s.elapsed_time(e))
+        C = dC.cpu().numpy().view(np.uint64).reshape(count, W)
+        for i in {0, count - 1}:
+            if not np.array_equal(C[i], oracle.inv_cyclic(A[i], n)):
+                raise AssertionError("inverse %d at n=%d differs from the oracle" % (i, n))
+        ms = float(np.median(ts))
+        key = "single" if count == 1 else "batch_%d" % count
+        out[key] = {"ms": round(ms, 4), "inverses_per_s": round(count / (ms * 1e-3), 1)}
+    return out
+
+
 def check_sample(res, n, count, k=6):
     """Spot-check k items against the oracle and all items against parity."""
     import numpy as np
@@ -405,6 +446,7 @@ def main():
     mixed = None
     serving = []
     single = None
+    inverse = None
     if not args.only_n:
         log("single product latency n=12323 (1000 calls after 100 warm-ups)")
         single = single_latency(ctx, 12323, 1000, 100, inputs.SEED_BASE + 1)
@@ -412,6 +454,9 @@ def main():
         log("mixed workload: 8192 products, six sizes, half dense x sparse")
         mixed = time_mixed(ctx, 10, inputs.SEED_BASE + 4)
         log("  %s" % mixed)
+        log("inverses in F2[X]/(X^12323 - 1): one, and a batch of 1024")
+        inverse = time_inverse(ctx, 12323, inputs.SEED_BASE + 9)
+        log("  %s" % inverse)
         if not args.no_serving:
             from paper_2201_10473_amd import serve
 
@@ -465,6 +510,7 @@ def main():
              for n, r in results.items()},
             shared_operand=shared,
             single_product=single,
+            inverse=inverse,
             mixed=mixed,
             serving=serving,
         ),

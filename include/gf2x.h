@@ -144,6 +144,24 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count,
 int gf2x_schedule_info(gf2x_ctx *ctx, uint32_t n_bits, uint32_t *padded_words32,
                        uint64_t *base_products, uint64_t *lane_ops, char *name, size_t name_len);
 
+/* Inverses in F2[X]/(X^n - 1) for the BIKE rings: c_i = a_i^(2^(n-1) - 2) for
+ * the `count` items (all with the same n_bits = n and kind GF2X_KIND_CYCLIC;
+ * b_off is ignored).  n must be an odd prime (as the BIKE block lengths
+ * 12323, 24659 and 40973 are; there 2 is moreover primitive modulo n, so the
+ * units are exactly the elements of odd weight).  X^n - 1 is then X + 1 times
+ * irreducibles of degree ord_n(2), which divides n - 1, so c_i is the inverse
+ * of a_i whenever a_i is invertible (for other a_i, c_i is that power, not an
+ * inverse; nothing is checked, since checking would depend on the operand).
+ * The sequence of operations depends only on n and count: about log2(n)
+ * batched products (the same kernels as gf2x_mul_batched) and as many
+ * repeated squarings, each a public bit permutation.  c_base + c_off[i] may
+ * overlap a_base + a_off[i].  Uses a context workspace of about 4 * count *
+ * W(n) words (within the budget), ordered by the context's event.
+ * Errors: GF2X_EINVAL (arguments, or n not an odd prime), GF2X_ENOMEM,
+ * GF2X_EDEVICE. */
+int gf2x_inv_cyclic_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint64_t *c_base,
+                            const uint64_t *a_base, uint32_t flags, gf2x_stream_t stream);
+
 /* Autotuner.  For each n in sizes[0..nsizes), time every size class whose
  * padded size holds n (up to 1.6x padding) on a batch of `batch` ring
  * products of synthetic operands in a temporary device buffer (contents do

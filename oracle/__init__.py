@@ -1,4 +1,5 @@
-"""CPU oracle for products in F2[X] and F2[X]/(X^n - 1).
+"""CPU oracle for products in F2[X] and F2[X]/(X^n - 1), and for inverses in
+F2[X]/(X^n - 1).
 
 TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
 leg of the benchmark may import this package; the product library never does.
@@ -9,6 +10,7 @@ from .oracle import (  # noqa: F401
     build,
     clmul64,
     fold,
+    inv_cyclic,
     load,
     mul,
     mul_cyclic,

@@ -118,3 +118,61 @@ def mul_cyclic_many(a, b, n):
     if rc:
         raise RuntimeError("gf2x_ref_mul_cyclic_many failed (%d)" % rc)
     return r
+
+
+# ------------------------------------------------------------------ inverses
+# The inverse in F2[X]/(X^n - 1) by its definition: c with a*c = 1 modulo
+# X^n - 1, found by the extended Euclidean algorithm on polynomials over F2
+# held as Python integers (bit i = coefficient of X^i).  This is independent
+# of the library's method (an exponentiation by repeated squarings and
+# products); it exists when gcd(a, X^n - 1) = 1.
+
+
+def _to_int(a, n):
+    a = _as_words(a, n)
+    x = 0
+    for i, w in enumerate(a.tolist()):
+        x |= int(w) << (64 * i)
+    return x & ((1 << n) - 1)
+
+
+def _from_int(x, n):
+    return np.array([(x >> (64 * i)) & 0xFFFFFFFFFFFFFFFF for i in range(words(n))], dtype=np.uint64)
+
+
+def _pmul(x, y):
+    """Carry-less product of two integers (polynomials over F2)."""
+    if x.bit_length() < y.bit_length():
+        x, y = y, x
+    r = 0
+    while y:
+        low = y & -y
+        r ^= x << (low.bit_length() - 1)
+        y ^= low
+    return r
+
+
+def _pdivmod(x, y):
+    """Quotient and remainder of polynomial division over F2 (y != 0)."""
+    q = 0
+    dy = y.bit_length()
+    while x.bit_length() >= dy:
+        s = x.bit_length() - dy
+        q |= 1 << s
+        x ^= y << s
+    return q, x
+
+
+def inv_cyclic(a, n):
+    """Inverse of a in F2[X]/(X^n - 1) as words(n) words, or None if a shares
+    a factor with X^n - 1 (for instance when a has even weight)."""
+    m = (1 << n) | 1  # X^n - 1 = X^n + 1 over F2
+    r0, r1 = m, _to_int(a, n)
+    s0, s1 = 0, 1  # invariant: r_i = s_i * a (mod m)
+    while r1:
+        q, r = _pdivmod(r0, r1)
+        r0, r1 = r1, r
+        s0, s1 = s1, s0 ^ _pmul(q, s1)
+    if r0 != 1:
+        return None
+    return _from_int(_pdivmod(s0, m)[1], n)

@@ -328,6 +328,27 @@ int single_product(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t
     return GF2X_OK;
 }
 
+// n an odd prime: X^n - 1 is then (X + 1) times irreducibles of degree
+// ord_n(2), which divides n - 1, so every unit u of F2[X]/(X^n - 1) has
+// u^(2^(n-1) - 1) = 1.
+bool odd_prime(uint32_t n) {
+    if (n < 3 || n % 2 == 0) return false;
+    for (uint32_t d = 3; (uint64_t)d * d <= n; d += 2)
+        if (n % d == 0) return false;
+    return true;
+}
+
+// 2^(-j) mod the prime n (2^(n-1) = 1).
+uint32_t inv_pow2(uint32_t n, uint64_t j) {
+    uint64_t e = (n - 1) - j % (n - 1), r = 1, b = 2 % n;
+    while (e) {
+        if (e & 1) r = r * b % n;
+        b = b * b % n;
+        e >>= 1;
+    }
+    return (uint32_t)r;
+}
+
 }  // namespace
 
 extern "C" {
@@ -393,6 +414,7 @@ void gf2x_destroy(gf2x_ctx *ctx) {
         if (kv.second.staged_ws) hipFree(kv.second.staged_ws);
     }
     if (ctx->staged_ws) hipFree(ctx->staged_ws);
+    if (ctx->inv_ws) hipFree(ctx->inv_ws);
     toeplitz::release(ctx->tz);
     for (int i = 0; i < gf2x_ctx::kForks; ++i)
         if (ctx->fork_stream[i]) hipStreamDestroy(ctx->fork_stream[i]);
@@ -531,6 +553,91 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
     HIP_TRY(hipMemcpyAsync(ctx->d_items, host.data(), count * sizeof(DevItem), hipMemcpyHostToDevice, s));
     rc = launch_groups(ctx, ctx->d_items, groups, c_base, a_base, b_base, ctx->staged_ws, s);
     if (rc) return rc;
+    HIP_TRY(hipEventRecord(ctx->ws_free, s));
+    ctx->ws_used = true;
+    return GF2X_OK;
+}
+
+// Inversion by exponentiation (the Itoh-Tsujii addition chain): for an odd
+// prime n, an invertible a has a^(2^(n-1) - 1) = 1, so a^-1 =
+// a^(2^(n-1) - 2) = (a^(2^(n-2) - 1))^2.  b_k = a^(2^k - 1) follows the
+// binary digits of m = n - 2 from the top: b_2k = b_k^(2^k) * b_k, and
+// b_(k+1) = b_k^2 * a.  Squaring j times is a bit permutation; every step
+// runs on all items at once (one permutation launch, one batched product).
+int gf2x_inv_cyclic_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint64_t *c_base,
+                            const uint64_t *a_base, uint32_t flags, gf2x_stream_t stream) {
+    if (!ctx || (count && (!items || !c_base || !a_base))) return GF2X_EINVAL;
+    if (flags != 0) return GF2X_EINVAL;
+    if (count == 0) return GF2X_OK;
+    const uint32_t n = items[0].n_bits;
+    for (uint32_t i = 0; i < count; ++i)
+        if (items[i].n_bits != n || items[i].kind != GF2X_KIND_CYCLIC) return GF2X_EINVAL;
+    if (n > kMaxBits || !odd_prime(n)) return GF2X_EINVAL;
+    if (!aligned8(c_base) || !aligned8(a_base)) return GF2X_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipSetDevice(ctx->device));
+    const uint64_t W = words64(n);
+    const uint32_t w32 = (n + 31u) / 32u;
+    const int cls = count <= 64 ? ctx->single_of_w32[w32] : ctx->cls_of_w32[w32];
+    // working buffers: A (a), X (b_k), Y, Z, then the offsets and descriptors
+    const size_t buf = (size_t)count * W * 8;
+    const size_t offs = ((size_t)count * 8 + 255) / 256 * 256;
+    const size_t need = 4 * ((buf + 255) / 256 * 256) + 2 * offs + (size_t)count * sizeof(DevItem);
+    int rc = ensure_ws(ctx, ctx->inv_ws, ctx->inv_ws_bytes, need, ctx->ws_free, ctx->ws_used);
+    if (rc) return rc;
+    Group g{cls, 0, count};
+    if (class_info(cls).child >= 0) {
+        rc = ensure_ws(ctx, ctx->staged_ws, ctx->staged_ws_bytes, (staged_workspace_bytes(cls, count) + 255) / 256 * 256,
+                       ctx->ws_free, ctx->ws_used);
+        if (rc == GF2X_ENOMEM) g.cls = class_info(cls).direct;
+        else if (rc) return rc;
+    }
+    char *p = reinterpret_cast<char *>(ctx->inv_ws);
+    const size_t stride = (buf + 255) / 256 * 256;
+    uint64_t *A = reinterpret_cast<uint64_t *>(p);
+    uint64_t *X = reinterpret_cast<uint64_t *>(p + stride);
+    uint64_t *Y = reinterpret_cast<uint64_t *>(p + 2 * stride);
+    uint64_t *Z = reinterpret_cast<uint64_t *>(p + 3 * stride);
+    uint64_t *d_aoff = reinterpret_cast<uint64_t *>(p + 4 * stride);
+    uint64_t *d_coff = reinterpret_cast<uint64_t *>(p + 4 * stride + offs);
+    DevItem *d_it = reinterpret_cast<DevItem *>(p + 4 * stride + 2 * offs);
+    std::vector<uint64_t> ho(2 * (size_t)count);
+    std::vector<DevItem> hi(count);
+    for (uint32_t i = 0; i < count; ++i) {
+        ho[i] = items[i].a_off;
+        ho[count + i] = items[i].c_off;
+        hi[i] = DevItem{n, kKindCyclic, (uint32_t)g.cls, 0u, i * W, i * W, i * W};
+    }
+    if (ctx->ws_used) HIP_TRY(hipStreamWaitEvent(s, ctx->ws_free, 0));
+    HIP_TRY(hipMemcpyAsync(d_aoff, ho.data(), count * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_coff, ho.data() + count, count * 8, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(d_it, hi.data(), count * sizeof(DevItem), hipMemcpyHostToDevice, s));
+    HIP_TRY(launch_gather_items(a_base, d_aoff, A, n, count, s));
+    HIP_TRY(hipMemcpyAsync(X, A, buf, hipMemcpyDeviceToDevice, s));
+    const uint32_t m = n - 2;
+    int top = 31;
+    while (!((m >> top) & 1u)) --top;
+    uint64_t k = 1;
+    auto product = [&](const uint64_t *f, const uint64_t *h, uint64_t *out) -> int {
+        char *ws = reinterpret_cast<char *>(ctx->staged_ws);
+        return launch_one(ctx, g, d_it, ws, out, f, h, s);
+    };
+    for (int bit = top - 1; bit >= 0; --bit) {
+        HIP_TRY(launch_frobenius(X, Y, nullptr, n, count, inv_pow2(n, k), s));  // b^(2^k)
+        rc = product(Y, X, Z);                                                  // b_2k
+        if (rc) return rc;
+        std::swap(X, Z);
+        k *= 2;
+        if ((m >> bit) & 1u) {
+            HIP_TRY(launch_frobenius(X, Y, nullptr, n, count, inv_pow2(n, 1), s));  // b^2
+            rc = product(Y, A, Z);                                                  // b_(k+1)
+            if (rc) return rc;
+            std::swap(X, Z);
+            k += 1;
+        }
+    }
+    if (k != m) return GF2X_EINVAL;  // cannot happen: the chain follows the digits of m
+    HIP_TRY(launch_frobenius(X, c_base, d_coff, n, count, inv_pow2(n, 1), s));  // (b_m)^2
     HIP_TRY(hipEventRecord(ctx->ws_free, s));
     ctx->ws_used = true;
     return GF2X_OK;

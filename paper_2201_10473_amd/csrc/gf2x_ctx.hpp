@@ -41,6 +41,8 @@ struct gf2x_ctx {
     hipEvent_t ws_free = nullptr;  // recorded after the last launch reading d_items / staged_ws
     void *staged_ws = nullptr;     // workspace of staged classes (point operands and products)
     size_t staged_ws_bytes = 0;
+    void *inv_ws = nullptr;        // working buffers of gf2x_inv_cyclic_batched (same guard)
+    size_t inv_ws_bytes = 0;
     bool ws_used = false;
     std::map<std::tuple<const void *, uint32_t, const void *, const void *, const void *, uint32_t, void *>,
              gf2x::GraphEntry>

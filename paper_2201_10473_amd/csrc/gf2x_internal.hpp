@@ -54,4 +54,13 @@ hipError_t launch_convert_items(const struct gf2x_item *items, uint32_t count, D
 hipError_t launch_mixed(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
                         const uint64_t *b_base, const uint8_t *cls_of_w32, int num_cu, hipStream_t s);
 
+// Inversion helpers (gf2x_inv.hip): items of W(n) words.
+// out item i = in item i (contiguous) squared j times, inv = 2^(-j) mod n;
+// written at out_base + out_off[i] (device array) or contiguously if null.
+hipError_t launch_frobenius(const uint64_t *in, uint64_t *out_base, const uint64_t *out_off, uint32_t n, uint32_t count,
+                            uint32_t inv, hipStream_t s);
+// out item i (contiguous) = in_base + in_off[i] (device array), bits >= n cleared.
+hipError_t launch_gather_items(const uint64_t *in_base, const uint64_t *in_off, uint64_t *out, uint32_t n,
+                               uint32_t count, hipStream_t s);
+
 }  // namespace gf2x

@@ -1,0 +1,68 @@
+// gf2x_inv.hip -- kernels of the inversion in F2[X]/(X^n - 1): repeated
+// squaring as a bit permutation, and the gathers that move operands between
+// the caller's buffers and the contiguous working buffers.
+//
+// In characteristic 2, squaring is linear: (sum a_i X^i)^2 = sum a_i X^(2i),
+// so squaring j times modulo X^n - 1 sends coefficient i to i * 2^j mod n.
+// Output bit t is input bit t * 2^(-j) mod n; the permutation depends only on
+// the public n and j, never on operand bits (constant time).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gf2x_internal.hpp"
+
+namespace gf2x {
+
+// out item i (W words at out_base + (out_off ? out_off[i] : i * W)) = in item
+// i (W words at in + i * W) squared j times, with inv = 2^(-j) mod n.  One
+// thread per output word; bits >= n of the last word are written zero.
+__global__ void k_frobenius(const uint64_t *in, uint64_t *out_base, const uint64_t *out_off, uint32_t n,
+                            uint32_t W, uint32_t count, uint32_t inv) {
+    const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (g >= (uint64_t)count * W) return;
+    const uint32_t i = (uint32_t)(g / W), w = (uint32_t)(g - (uint64_t)i * W);
+    const uint64_t *src = in + (uint64_t)i * W;
+    uint64_t v = 0;
+    for (uint32_t b = 0; b < 64; ++b) {
+        const uint32_t t = 64u * w + b;
+        if (t < n) {
+            const uint32_t s = (uint32_t)(((uint64_t)t * inv) % n);
+            v |= ((src[s >> 6] >> (s & 63u)) & 1ull) << b;
+        }
+    }
+    uint64_t *dst = out_base + (out_off ? out_off[i] : (uint64_t)i * W);
+    dst[w] = v;
+}
+
+// out item i (contiguous, W words) = the W words at in_base + in_off[i], bits
+// >= n cleared.
+__global__ void k_gather_items(const uint64_t *in_base, const uint64_t *in_off, uint64_t *out, uint32_t n, uint32_t W,
+                               uint32_t count) {
+    const uint64_t g = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x;
+    if (g >= (uint64_t)count * W) return;
+    const uint32_t i = (uint32_t)(g / W), w = (uint32_t)(g - (uint64_t)i * W);
+    uint64_t v = in_base[in_off[i] + w];
+    const uint32_t s = n % 64u;
+    if (w == W - 1 && s) v &= (1ull << s) - 1ull;
+    out[g] = v;
+}
+
+hipError_t launch_frobenius(const uint64_t *in, uint64_t *out_base, const uint64_t *out_off, uint32_t n, uint32_t count,
+                            uint32_t inv, hipStream_t s) {
+    const uint32_t W = (n + 63u) / 64u;
+    const uint64_t total = (uint64_t)count * W;
+    hipLaunchKernelGGL(k_frobenius, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, in, out_base, out_off, n,
+                       W, count, inv);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_items(const uint64_t *in_base, const uint64_t *in_off, uint64_t *out, uint32_t n,
+                               uint32_t count, hipStream_t s) {
+    const uint32_t W = (n + 63u) / 64u;
+    const uint64_t total = (uint64_t)count * W;
+    hipLaunchKernelGGL(k_gather_items, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, s, in_base, in_off, out, n,
+                       W, count);
+    return hipGetLastError();
+}
+
+}  // namespace gf2x

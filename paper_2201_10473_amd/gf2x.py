@@ -120,6 +120,8 @@ def load():
         fn.restype = ctypes.c_int
     lib.gf2x_mul_batched.argtypes = [vp, vp, u32, vp, vp, vp, u32, vp]
     lib.gf2x_mul_batched.restype = ctypes.c_int
+    lib.gf2x_inv_cyclic_batched.argtypes = [vp, vp, u32, vp, vp, u32, vp]
+    lib.gf2x_inv_cyclic_batched.restype = ctypes.c_int
     lib.gf2x_schedule_info.argtypes = [
         vp, u32, ctypes.POINTER(u32), ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.c_char_p, sz
     ]
@@ -238,6 +240,17 @@ class Context:
                 _stream(stream),
             ),
             "gf2x_mul_batched",
+        )
+
+    def inv_cyclic_batched(self, items, c_base, a_base, stream=None):
+        """Inverses in F2[X]/(X^n - 1) (n prime, 2 primitive modulo n) of the
+        items' operands a_base + a_off, written at c_base + c_off."""
+        items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
+        _check(
+            self._lib.gf2x_inv_cyclic_batched(
+                self._h, items.ctypes.data, len(items), _ptr(c_base), _ptr(a_base), 0, _stream(stream)
+            ),
+            "gf2x_inv_cyclic_batched",
         )
 
     def tune(self, sizes, batch=4096, out_path=None):
