@@ -445,6 +445,7 @@ def main():
 
     mixed = None
     serving = []
+    trace = None
     single = None
     inverse = None
     if not args.only_n:
@@ -470,6 +471,12 @@ def main():
                     serving.append(res)
                     log("  achieved %.0f req/s p50 %.1f us p99 %.1f us" % (res["achieved_rate"], res["p50_us"],
                                                                            res["p99_us"]))
+                from paper_2201_10473_amd import hqc_trace
+
+                log("HQC-shaped trace: 5000 operations (chains of 1-3 dependent products), 20000 op/s")
+                trace, tbufs = hqc_trace.run(sctx, 20000, 5000, inputs.SEED_BASE + 11)
+                trace["checked_products"] = hqc_trace.check_against_batched(sctx, tbufs)
+                log("  %s" % trace["per_kind"])
 
     head = sizes[0]
     main_res = results[head]
@@ -513,6 +520,7 @@ def main():
             inverse=inverse,
             mixed=mixed,
             serving=serving,
+            hqc_trace=trace,
         ),
     }
     if not args.no_cpu_baseline:
