@@ -128,8 +128,13 @@ int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_
  * first time a given (items, count, bases, flags, stream) is seen and
  * replays it afterwards; the host item array must then stay unchanged.
  * count == 0 is a no-op.
+ * A stream under capture is refused with GF2X_ENOTSUP: the call orders the
+ * context's workspace with the context's event and writes descriptors to
+ * context-owned buffers, which a graph recorded from it could not replay
+ * safely.  GF2X_USE_GRAPH records and replays a graph that owns its own
+ * descriptors and workspace.
  * Errors: GF2X_EINVAL, GF2X_ENOMEM, GF2X_EDEVICE, GF2X_ENOTSUP (FORCE_TOEPLITZ
- * without SHARED_A, or device items with GF2X_USE_GRAPH). */
+ * without SHARED_A, device items with GF2X_USE_GRAPH, or a capturing stream). */
 int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count,
                      uint64_t *c_base, const uint64_t *a_base, const uint64_t *b_base,
                      uint32_t flags, gf2x_stream_t stream);
@@ -156,9 +161,11 @@ int gf2x_schedule_info(gf2x_ctx *ctx, uint32_t n_bits, uint32_t *padded_words32,
  * batched products (the same kernels as gf2x_mul_batched) and as many
  * repeated squarings, each a public bit permutation.  c_base + c_off[i] may
  * overlap a_base + a_off[i].  Uses a context workspace of about 4 * count *
- * W(n) words (within the budget), ordered by the context's event.
+ * W(n) words (within the budget), ordered by the context's event; for that
+ * reason a stream under capture is refused (GF2X_ENOTSUP), as in
+ * gf2x_mul_batched.
  * Errors: GF2X_EINVAL (arguments, or n not an odd prime), GF2X_ENOMEM,
- * GF2X_EDEVICE. */
+ * GF2X_EDEVICE, GF2X_ENOTSUP. */
 int gf2x_inv_cyclic_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint64_t *c_base,
                             const uint64_t *a_base, uint32_t flags, gf2x_stream_t stream);
 

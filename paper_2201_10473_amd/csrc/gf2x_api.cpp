@@ -441,6 +441,18 @@ int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_
     return single_product(ctx, c, a, b, n_bits, kKindCyclic, reinterpret_cast<hipStream_t>(stream));
 }
 
+// The batched calls refuse a stream under capture: they order the context's
+// workspace with the context's event, write descriptors into context-owned
+// buffers that later calls reuse or reallocate, and copy host descriptors
+// from memory that is gone once the call returns.  A graph recorded from
+// them could not be replayed safely; GF2X_USE_GRAPH records one that can.
+static int refuse_capture(hipStream_t s) {
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    const hipError_t e = hipStreamIsCapturing(s, &cap);
+    if (e != hipSuccess) return device_error(e);
+    return cap == hipStreamCaptureStatusNone ? GF2X_OK : GF2X_ENOTSUP;
+}
+
 int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint64_t *c_base,
                      const uint64_t *a_base, const uint64_t *b_base, uint32_t flags, gf2x_stream_t stream) {
     if (!ctx) return GF2X_EINVAL;
@@ -456,6 +468,7 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
     if (dev_items && (flags & (GF2X_USE_GRAPH | GF2X_SHARED_A))) return GF2X_ENOTSUP;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_TRY(hipSetDevice(ctx->device));
+    if (int rc = refuse_capture(s)) return rc;
 
     if (dev_items) {
         // Descriptors stay on the device; the class comes from the size table.
@@ -576,6 +589,7 @@ int gf2x_inv_cyclic_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t coun
     if (!aligned8(c_base) || !aligned8(a_base)) return GF2X_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     HIP_TRY(hipSetDevice(ctx->device));
+    if (int rc = refuse_capture(s)) return rc;
     const uint64_t W = words64(n);
     const uint32_t w32 = (n + 31u) / 32u;
     const int cls = count <= 64 ? ctx->single_of_w32[w32] : ctx->cls_of_w32[w32];

@@ -225,6 +225,50 @@ def test_single_products_staged_and_captured(ctx):
             assert np.array_equal(from_dev(dC), ref), (n, rep)
 
 
+def test_batched_calls_refuse_stream_capture(ctx):
+    """Batched products (host or device descriptors) and batched inverses on a
+    stream under capture return GF2X_ENOTSUP and record nothing; the capture
+    stays valid, and the same calls work eagerly afterwards."""
+    import torch
+    n, count = 12323, 4
+    W = oracle.words(n)
+    A = inputs.dense_batch(n, count, SEED + 10, 0)
+    B = inputs.dense_batch(n, count, SEED + 10, 1)
+    offs = np.arange(count) * W
+    items = gf2x.make_items(n, gf2x.KIND_CYCLIC, offs, offs, offs)
+    d_items = torch.from_numpy(items.view(np.uint8).copy()).cuda()
+    dA, dB, dC = to_dev(A.ravel()), to_dev(B.ravel()), empty_dev(count * W)
+    marker = torch.zeros(8, dtype=torch.int64, device="cuda")
+    calls = {
+        "host items": lambda: ctx.mul_batched(items, dC, dA, dB),
+        "host items, graph": lambda: ctx.mul_batched(items, dC, dA, dB, gf2x.USE_GRAPH),
+        "device items": lambda: ctx.mul_batched(d_items, dC, dA, dB, gf2x.ITEMS_ON_DEVICE, count=count),
+        "inverse": lambda: ctx.inv_cyclic_batched(items, dC, dA),
+    }
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    print("case batched calls under capture", flush=True)
+    codes = {}
+    with torch.cuda.graph(g):
+        marker.add_(1)
+        for name, call in calls.items():
+            try:
+                call()
+                codes[name] = gf2x.GF2X_OK
+            except gf2x.Gf2xError as e:
+                codes[name] = e.code
+    assert codes == {name: gf2x.GF2X_ENOTSUP for name in calls}, codes
+    g.replay()
+    torch.cuda.synchronize()
+    assert int(marker[0]) == 1
+    print("case batched calls eager after capture", flush=True)
+    ctx.mul_batched(items, dC, dA, dB)
+    torch.cuda.synchronize()
+    C = from_dev(dC).reshape(count, W)
+    for i in range(count):
+        assert np.array_equal(C[i], oracle.mul_cyclic(A[i], B[i], n)), i
+
+
 def test_batched_device_items(ctx):
     import torch
     n = 35851
