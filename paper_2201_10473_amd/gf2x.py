@@ -243,8 +243,10 @@ class Context:
         )
 
     def inv_cyclic_batched(self, items, c_base, a_base, stream=None):
-        """Inverses in F2[X]/(X^n - 1) (n prime, 2 primitive modulo n) of the
-        items' operands a_base + a_off, written at c_base + c_off."""
+        """Inverses in F2[X]/(X^n - 1) (n an odd prime; all items of one n) of
+        the items' operands a_base + a_off, written at c_base + c_off.  For an
+        operand that is not invertible the result is a_i^(2^(n-1) - 2), not an
+        inverse."""
         items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
         _check(
             self._lib.gf2x_inv_cyclic_batched(
