@@ -23,6 +23,7 @@
 // it, so an open-loop arrival process can be replayed exactly and latency is
 // measured from the scheduled arrival to the completion stamp.
 #include <hip/hip_runtime.h>
+#include <sys/prctl.h>
 
 #include <algorithm>
 #include <atomic>
@@ -62,6 +63,8 @@ constexpr int kSubStreams = 6;  // one per size class present in a batch
 // the lowest single-product latency (a staged class spreads a product over
 // several workgroups); larger batches use the fastest direct classes.
 constexpr uint32_t kSmallBatch = 64;
+// While batches run, the scheduler checks their completion events this often.
+constexpr uint64_t kBusyPollNs = 5000;
 
 struct Slot {
     hipStream_t stream = nullptr;
@@ -269,7 +272,22 @@ bool launch(gf2x_srv *srv) {
 }
 
 void scheduler(gf2x_srv *srv) {
-    hipSetDevice(srv->ctx->device);
+    const hipError_t dev = hipSetDevice(srv->ctx->device);
+    if (dev != hipSuccess) {
+        // nothing can run on this thread: report it (waking any drain) and admit nothing
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->error = GF2X_EDEVICE;
+            srv->error_text = hipGetErrorName(dev);
+        }
+        srv->cv.notify_all();
+        return;
+    }
+    // The idle waits below last 2-20 us.  Linux lets a sleeping thread wake up
+    // to its timer slack late (50 us by default), which would delay every
+    // admission and every completion stamp by up to that much; 1 ns keeps the
+    // wake-ups at the requested times.
+    prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
     while (true) {
         const size_t done = retire(srv);
         const bool launched = launch(srv);
@@ -290,7 +308,7 @@ void scheduler(gf2x_srv *srv) {
                 }
                 bool any_busy = false;
                 for (const Slot &s : srv->slots) any_busy |= s.busy;
-                if (any_busy) wait_ns = std::min<uint64_t>(wait_ns, 5000);
+                if (any_busy) wait_ns = std::min<uint64_t>(wait_ns, kBusyPollNs);
                 if (wait_ns > 2000) srv->cv.wait_for(lk, std::chrono::nanoseconds(wait_ns));
             }
         }
@@ -432,19 +450,20 @@ void gf2x_srv_destroy(gf2x_srv *srv) {
         srv->cv.notify_all();
         srv->thread.join();
     }
+    // Teardown returns nothing, so failures here have no one to be reported to.
     for (Slot &sl : srv->slots) {
-        if (sl.stream) hipStreamSynchronize(sl.stream);
-        if (sl.dev) hipFree(sl.dev);
-        if (sl.ws) hipFree(sl.ws);
-        if (sl.host) hipHostFree(sl.host);
-        if (sl.done) hipEventDestroy(sl.done);
-        if (sl.fork) hipEventDestroy(sl.fork);
+        if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+        if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.ws) (void)hipFree(sl.ws);
+        if (sl.host) (void)hipHostFree(sl.host);
+        if (sl.done) (void)hipEventDestroy(sl.done);
+        if (sl.fork) (void)hipEventDestroy(sl.fork);
         for (int k = 0; k < kSubStreams; ++k) {
-            if (sl.sub[k]) hipStreamSynchronize(sl.sub[k]);
-            if (sl.sub[k]) hipStreamDestroy(sl.sub[k]);
-            if (sl.join[k]) hipEventDestroy(sl.join[k]);
+            if (sl.sub[k]) (void)hipStreamSynchronize(sl.sub[k]);
+            if (sl.sub[k]) (void)hipStreamDestroy(sl.sub[k]);
+            if (sl.join[k]) (void)hipEventDestroy(sl.join[k]);
         }
-        if (sl.stream) hipStreamDestroy(sl.stream);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
     delete srv;
 }

@@ -50,6 +50,20 @@ def make_trace(count, seed):
     return kinds, ns, length, W.astype(np.uint64), X, opnd_off, R, res_off
 
 
+def _timer_slack(ns):
+    """Set this thread's Linux timer slack (how late a sleep may end); returns
+    the previous value, or None where it cannot be set."""
+    try:
+        import ctypes
+        libc = ctypes.CDLL(None, use_errno=True)
+        old = libc.prctl(30, 0, 0, 0, 0)  # PR_GET_TIMERSLACK
+        if old < 0 or libc.prctl(29, ctypes.c_ulong(ns), 0, 0, 0) != 0:  # PR_SET_TIMERSLACK
+            return None
+        return old
+    except (OSError, AttributeError):
+        return None
+
+
 def drive(srv, trace, arrival):
     """Serve the trace's operations through `srv` (a gf2x.Server, or any object
     with its submit / completion / now_ns methods).  The driver plays the
@@ -59,6 +73,17 @@ def drive(srv, trace, arrival):
     lie in the future.  Returns the completion stamp of each operation's last
     product and the number of products submitted."""
     kinds, ns, length, W, X, xo, R, ro = trace
+    # the polls below sleep 10 us; with the default 50 us slack every link
+    # of a chain would wait for the driver rather than for the server
+    old_slack = _timer_slack(1)
+    try:
+        return _drive(srv, ns, length, W, X, xo, R, ro, arrival)
+    finally:
+        if old_slack is not None:
+            _timer_slack(old_slack)
+
+
+def _drive(srv, ns, length, W, X, xo, R, ro, arrival):
     count = len(ns)
     active = []  # submissions in flight: [first ticket, operations, steps, handled]
     done_at = np.zeros(count, dtype=np.uint64)
