@@ -191,7 +191,7 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
  * stay within hbm_budget_bytes.  Requests whose arrival time has passed are
  * admitted into free slots in submission order; while a slot's batch runs,
  * later arrivals form the next batch on another slot, so their work overlaps
- * on the device.  A batch of at most 64 requests runs each product in its
+ * on the device.  A batch of at most 256 requests runs each product in its
  * size's lowest-latency class (possibly staged, using a per-slot workspace
  * that is part of the budget when the budget allows it); larger batches run
  * one workgroup per product.  Results are identical to gf2x_mul_cyclic of the

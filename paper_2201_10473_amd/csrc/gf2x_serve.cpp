@@ -61,8 +61,11 @@ struct Request {
 constexpr int kSubStreams = 6;  // one per size class present in a batch
 // A batch of at most this many requests runs each product in the class with
 // the lowest single-product latency (a staged class spreads a product over
-// several workgroups); larger batches use the fastest direct classes.
-constexpr uint32_t kSmallBatch = 64;
+// several workgroups); larger batches use the fastest direct classes.  Up to
+// a few hundred requests the device is far from full, so spreading products
+// shortens the batch; each slot then holds a staged workspace for this many
+// requests (about 14 MB at n = 57637).
+constexpr uint32_t kSmallBatch = 256;
 // While batches run, the scheduler checks their completion events this often.
 constexpr uint64_t kBusyPollNs = 5000;
 

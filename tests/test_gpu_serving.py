@@ -57,6 +57,22 @@ def test_high_rate_batches_overlap(ctx):
     serve.check_against_batched(ctx, *bufs)
 
 
+def test_burst_takes_batches_above_the_staged_threshold(ctx):
+    """1000 requests submitted at once are admitted as batches of several
+    hundred, which run one workgroup per product (direct classes), while a
+    trickle runs staged classes; both give the batched launch's results."""
+    print("case serving burst count=1000", flush=True)
+    ns, off, A, B = serve.make_requests(1000, inputs.SEED_BASE + 12)
+    C = np.zeros_like(A)
+    with gf2x.Server(ctx) as srv:
+        srv.submit(ns, A, off, B, off, C, off)
+        srv.drain()
+        st = srv.stats()
+    assert st["completed"] == 1000
+    assert st["max_batch_seen"] > 256
+    assert serve.check_against_batched(ctx, ns, off, A, B, C) == 1000
+
+
 def test_tiny_hbm_budget_backpressure(ctx):
     """A budget of one largest request per stream: every batch holds one
     request, nothing is dropped, results are unchanged."""
