@@ -193,8 +193,9 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
  * later arrivals form the next batch on another slot, so their work overlaps
  * on the device.  A batch of at most 256 requests runs each product in its
  * size's lowest-latency class (possibly staged, using a per-slot workspace
- * that is part of the budget when the budget allows it); larger batches run
- * one workgroup per product.  Results are identical to gf2x_mul_cyclic of the
+ * within half of the budget; with many streams or a small budget the limit
+ * is halved until the workspaces fit, down to none); larger batches run one
+ * workgroup per product.  Results are identical to gf2x_mul_cyclic of the
  * same operands (every class computes the same exact product). */
 typedef struct gf2x_srv gf2x_srv;
 

@@ -64,7 +64,8 @@ constexpr int kSubStreams = 6;  // one per size class present in a batch
 // several workgroups); larger batches use the fastest direct classes.  Up to
 // a few hundred requests the device is far from full, so spreading products
 // shortens the batch; each slot then holds a staged workspace for this many
-// requests (about 14 MB at n = 57637).
+// requests (about 14 MB at n = 57637).  Where the budget cannot hold that for
+// every slot, the limit is halved until it can.
 constexpr uint32_t kSmallBatch = 256;
 // While batches run, the scheduler checks their completion events this often.
 constexpr uint64_t kBusyPollNs = 5000;
@@ -91,6 +92,7 @@ struct gf2x_srv {
     uint32_t max_bits = 0, max_batch = 0, max_pending = 0;
     size_t slot_bytes = 0;
     size_t ws_bytes = 0;  // per slot; 0 when the budget leaves no room
+    uint32_t small_limit = 0;  // batches up to this size use the staged classes
     std::vector<Slot> slots;
     std::mutex mu;
     std::condition_variable cv;
@@ -189,7 +191,7 @@ bool launch(gf2x_srv *srv) {
     std::vector<DevItem> tmp(count);
     sl->c_off.resize(count);
     uint64_t off = 0;
-    const bool small = count <= kSmallBatch && srv->ws_bytes > 0;
+    const bool small = count <= srv->small_limit && srv->ws_bytes > 0;
     for (uint32_t i = 0; i < count; ++i) {
         const Request &r = sl->reqs[i];
         const uint64_t W = (r.n + 63u) / 64u;
@@ -337,12 +339,17 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
     const uint64_t Wmax = (max_bits + 63u) / 64u;
     const size_t per_req = sizeof(DevItem) + 3 * Wmax * 8;
     // workspace of the staged groups of a small batch: all of its requests in
-    // the staged class with the largest workspace, plus rounding per group
-    size_t ws_bytes = 0;
-    for (int c = 0; c < kNumClasses; ++c)
-        if (class_info(c).child >= 0) ws_bytes = std::max(ws_bytes, staged_workspace_bytes(c, kSmallBatch));
-    ws_bytes = round_up(ws_bytes + (size_t)kNumClasses * 1024, 256);
-    if (ws_bytes * streams * 2 > budget) ws_bytes = 0;  // keep most of the budget for the slots
+    // the staged class with the largest workspace, plus rounding per group.
+    // The slots' workspaces together take at most half of the budget.
+    auto ws_for = [](uint32_t limit) {
+        size_t w = 0;
+        for (int c = 0; c < kNumClasses; ++c)
+            if (class_info(c).child >= 0) w = std::max(w, staged_workspace_bytes(c, limit));
+        return round_up(w + (size_t)kNumClasses * 1024, 256);
+    };
+    uint32_t small_limit = kSmallBatch;
+    while (small_limit > 0 && ws_for(small_limit) * streams * 2 > budget) small_limit /= 2;
+    const size_t ws_bytes = small_limit ? ws_for(small_limit) : 0;
     uint64_t max_batch = (budget - ws_bytes * streams) / streams / per_req;
     if (o.max_batch && o.max_batch < max_batch) max_batch = o.max_batch;
     if (max_batch < 1) return GF2X_ENOMEM;  // the budget cannot hold one request per stream
@@ -354,6 +361,7 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
     srv->max_pending = o.max_pending ? o.max_pending : (1u << 22);
     srv->slot_bytes = round_up((size_t)srv->max_batch * sizeof(DevItem), 256) + 3 * (size_t)srv->max_batch * Wmax * 8;
     srv->ws_bytes = ws_bytes;
+    srv->small_limit = small_limit;
     srv->slots.resize(streams);
     hipError_t e = hipSetDevice(ctx->device);
     for (Slot &sl : srv->slots) {

@@ -73,6 +73,15 @@ def test_burst_takes_batches_above_the_staged_threshold(ctx):
     assert serve.check_against_batched(ctx, ns, off, A, B, C) == 1000
 
 
+def test_sixteen_streams_default_budget(ctx):
+    """With 16 slots the default budget holds the staged workspace for smaller
+    batches only; results still equal the batched launch."""
+    print("case serving streams=16 rate=100000 count=4000", flush=True)
+    res, bufs = serve.run(ctx, 100000, 4000, inputs.SEED_BASE + 13, streams=16)
+    assert res["server"]["completed"] == 4000
+    assert serve.check_against_batched(ctx, *bufs) == 4000
+
+
 def test_tiny_hbm_budget_backpressure(ctx):
     """A budget of one largest request per stream: every batch holds one
     request, nothing is dropped, results are unchanged."""
