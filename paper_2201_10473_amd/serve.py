@@ -70,8 +70,8 @@ def run(ctx, rate, count, seed, hbm_budget_bytes=0, streams=0, start_delay_s=0.0
     gaps = rng.exponential(1.0 / rate, count)
     with gf2x.Server(ctx, hbm_budget_bytes=hbm_budget_bytes, streams=streams, max_batch=max_batch) as srv:
         if warm:
-            # warm-up replay: 0.1 s of traffic at the same rate (at least 2000 requests)
-            k = warm_requests if warm_requests is not None else max(2000, int(rate * 0.1))
+            # warm-up replay: 0.3 s of traffic at the same rate (at least 2000 requests)
+            k = warm_requests if warm_requests is not None else max(2000, int(rate * 0.3))
             warm_up(srv, seed + 2, (ns, A, off, B, C), rate, k)
             base = srv.stats()
         else:
