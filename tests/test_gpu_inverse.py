@@ -7,6 +7,7 @@ import oracle
 from oracle import oracle as om
 from paper_2201_10473_amd import gf2x, inputs
 from tests.gpu_util import empty_dev, from_dev, to_dev
+from tests.oracle_check import ring_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -29,7 +30,8 @@ def odd_weight_batch(n, count, seed):
     return A
 
 
-@pytest.mark.parametrize("n,count", [(11, 9), (13, 5), (17, 7), (101, 33), (12323, 70), (24659, 3), (40973, 3)])
+@pytest.mark.parametrize("n,count", [(11, 9), (13, 5), (17, 7), (101, 33), (12323, 70), (12323, 1024), (24659, 3),
+                                     (40973, 3)])
 def test_inverse_matches_oracle(ctx, n, count):
     """Batches above 64 items use the batch schedule, smaller ones the
     single-product one; 17 is a prime for which 2 is not primitive."""
@@ -46,6 +48,15 @@ def test_inverse_matches_oracle(ctx, n, count):
     import torch
     torch.cuda.synchronize()
     C = from_dev(dC)
+    # every result: a * c = 1 with the oracle's product (the inverse is unique)
+    unit = np.zeros(W, dtype=np.uint64)
+    unit[0] = 1
+    Cr = np.stack([C[int(c_off[i]):int(c_off[i]) + W] for i in range(count)])
+    prod = ring_rows(A, Cr, n)
+    for i in range(count):
+        if n >= 1000 or bin(om._to_int(A[i], n)).count("1") % 2:
+            assert np.array_equal(prod[i], unit) or oracle.inv_cyclic(A[i], n) is None, (n, i)
+    # and the oracle's own inverse (extended Euclid) on a sample at large n
     sample = range(count) if n < 1000 else (0, 1, count - 1)
     for i in sample:
         got = C[int(c_off[i]):int(c_off[i]) + W]
