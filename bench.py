@@ -2,8 +2,9 @@
 
 Workload (one step): 4096 independent dense x dense ring products at
 n = 17669 (277 uint64 words per operand), uniform seeded operands, all in
-one persistent launch (replayed from a cached HIP graph).  Reported value:
-products per second over the timed steps, inputs already resident in HBM.
+one persistent launch (a recorded plan: one HIP graph replay per step).
+Reported value: products per second over the timed steps, inputs already
+resident in HBM.
 
 Also measured (reported under "extra"): the same batch at n = 57637, and
 both sizes as 4096 back-to-back single-product launches (one per product)
@@ -13,16 +14,19 @@ roofline: the dominant kernel is the batched product kernel; it is bound by
 VALU integer throughput.  achieved = modelled algorithmic lane-ops of the
 schedule (base-case bit operations plus XOR passes, as reported by
 gf2x_schedule_info) x products per launch / mean launch time, measured with
-HIP events on the launch stream over the timed steps; peak = 256 CU x 64
-lanes x 2.4 GHz.
+HIP events on the launch stream over the timed steps; peak = 256 CU x 4 SIMD
+x 32 lanes per clock x 2.4 GHz = 78.6 T lane-ops/s (a SIMD issues one 32-bit
+wave64 op every two clocks).
 
 cpu_baseline: the CPU oracle (word schoolbook + fold) timed on the host
-cores over a bounded sample of the same workload.
+over a bounded sample of the same workload: all usable cores (at most 16
+threads), and one thread pinned to one core; the CPU model is reported.
 """
 import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -60,25 +64,27 @@ def time_batched(ctx, n, count, steps, warmup, seed):
     from paper_2201_10473_amd import gf2x
 
     A, B, items, dA, dB, dC = make_batch(n, count, seed)
-    flags = gf2x.USE_GRAPH
     stream = torch.cuda.current_stream()
+    plan = ctx.plan(items, dC, dA, dB)
     # warm-up: the requested steps, and at least ~0.5 s of device work so the
     # engine clock has settled before the timed region
     t0 = time.perf_counter()
     done = 0
     while done < max(warmup, 1) or time.perf_counter() - t0 < 0.5:
-        ctx.mul_batched(items, dC, dA, dB, flags, stream)
+        plan.launch(stream)
         torch.cuda.synchronize()
         done += 1
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s, e in ev:
         s.record(stream)
-        ctx.mul_batched(items, dC, dA, dB, flags, stream)
+        plan.launch(stream)
         e.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     launch_ms = sum(s.elapsed_time(e) for s, e in ev) / steps
+    plan.close()
     return {"A": A, "B": B, "C": dC, "wall_s": wall, "launch_ms": launch_ms, "items": items}
 
 
@@ -212,6 +218,19 @@ def single_latency(ctx, n, calls, warmup, seed):
             "schedule": single_schedule(n)}
 
 
+def direct_class(n):
+    """The fastest direct class (one workgroup per product) of n: the third
+    column of the packaged schedule table."""
+    from paper_2201_10473_amd import gf2x
+
+    w = (n + 31) // 32
+    for line in open(gf2x.DEFAULT_TUNE_CACHE):
+        f = line.split()
+        if f and not line.startswith("#") and int(f[0]) == w and len(f) >= 3:
+            return f[2]
+    raise RuntimeError("no direct class for n=%d in the schedule table" % n)
+
+
 def single_schedule(n):
     """The class a single product of n bits runs in: the fourth column of the
     packaged schedule table (the lowest single-product latency measured), else
@@ -305,8 +324,21 @@ def check_sample(ctx, res, n, count, k=6):
     return C
 
 
+def cpu_model():
+    """CPU model name of the host (from /proc/cpuinfo), or None."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(n, seed, target_s=12.0):
-    """Oracle throughput on the host cores over a bounded sample of the workload."""
+    """Oracle throughput on the host over a bounded sample of the workload:
+    all usable cores (a thread pool, at most 16 threads) and one thread pinned
+    to one core."""
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
@@ -315,7 +347,8 @@ def cpu_baseline(n, seed, target_s=12.0):
     from paper_2201_10473_amd import inputs
 
     oracle.load()
-    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    cpus = sorted(os.sched_getaffinity(0))
+    threads = max(1, min(16, len(cpus)))
     A = inputs.dense_batch(n, 1, seed, 0)
     B = inputs.dense_batch(n, 1, seed, 1)
     t0 = time.perf_counter()
@@ -335,6 +368,16 @@ def cpu_baseline(n, seed, target_s=12.0):
     with ThreadPoolExecutor(max_workers=threads) as ex:
         list(ex.map(work, range(threads)))
     wall = time.perf_counter() - t0
+    # one thread pinned to one core, on a sample of about 3 s
+    k1 = max(1, min(total, int(3.0 / max(one, 1e-4))))
+    pinned = os.sched_getaffinity(0)
+    try:
+        os.sched_setaffinity(0, {cpus[0]})
+        t0 = time.perf_counter()
+        oracle.mul_cyclic_many(A[:k1], B[:k1], n)
+        wall1 = time.perf_counter() - t0
+    finally:
+        os.sched_setaffinity(0, pinned)
     return {
         "value": round(total / wall, 2),
         "unit": "products/s",
@@ -342,6 +385,11 @@ def cpu_baseline(n, seed, target_s=12.0):
         "kind": "oracle",
         "sample": "%d ring products at n=%d (the first %d pairs of the seeded batch), %d threads x %d products"
         % (total, n, total, threads, per_thread),
+        "single_core": {"value": round(k1 / wall1, 2), "unit": "products/s", "cores": 1,
+                        "sample": "%d ring products at n=%d on one thread pinned to cpu %d" % (k1, n, cpus[0])},
+        "host_cpus_usable": len(cpus),
+        "nproc": os.cpu_count(),
+        "cpu_model": cpu_model(),
     }
 
 
@@ -429,13 +477,30 @@ def main():
         }
         res["valu_frac"] = ops * BATCH / (res["launch_ms"] * 1e-3) / VALU_PEAK
         if not args.no_one_per_launch and not args.only_n:
-            log("one-per-launch n=%d" % n)
-            o = time_one_per_launch(ctx, n, BATCH, seed)
+            # one kernel launch per product: a context whose single-product
+            # class is the direct class of n (one workgroup, one launch)
+            direct = direct_class(n)
+            with tempfile.NamedTemporaryFile("w", suffix=".txt", delete=False) as f:
+                f.write("%d %s %s %s\n" % ((n + 31) // 32, name, direct, direct))
+                table = f.name
+            try:
+                with gf2x.Context(0, tune_cache=table) as dctx:
+                    log("one-per-launch n=%d (one %s launch per product)" % (n, direct))
+                    o = time_one_per_launch(dctx, n, BATCH, seed)
+            finally:
+                os.unlink(table)
             # same seeded operands as the batched run: every result must match it
             if not np.array_equal(o["C"].cpu().numpy().view(np.uint64).reshape(BATCH, -1), C_batched):
                 raise AssertionError("one-per-launch results differ from the batched launch at n=%d" % n)
+            res["one_per_launch_class"] = direct
             res["one_per_launch_products_per_s"] = BATCH / o["wall_s"]
             res["batched_over_one_per_launch"] = res["products_per_s"] / res["one_per_launch_products_per_s"]
+            log("one-per-launch n=%d through gf2x_mul_cyclic (lowest-latency class %s)" % (n, single_schedule(n)))
+            o = time_one_per_launch(ctx, n, BATCH, seed)
+            if not np.array_equal(o["C"].cpu().numpy().view(np.uint64).reshape(BATCH, -1), C_batched):
+                raise AssertionError("single-product results differ from the batched launch at n=%d" % n)
+            res["single_call_class"] = single_schedule(n)
+            res["single_call_products_per_s"] = BATCH / o["wall_s"]
         results[n] = res
         log("n=%d: %.0f products/s, launch %.3f ms, VALU frac %.3f" % (n, res["products_per_s"], res["launch_ms"], res["valu_frac"]))
 

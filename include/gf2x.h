@@ -126,7 +126,11 @@ int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_
  * library pick the Toeplitz MFMA path for that batch; the FORCE flags pin
  * the choice.  GF2X_USE_GRAPH captures the launch sequence in a HIP graph the
  * first time a given (items, count, bases, flags, stream) is seen and
- * replays it afterwards; the host item array must then stay unchanged.
+ * replays it afterwards.  A replay reads the host descriptors once to notice
+ * an edited array (then the batch is recorded again); the context keeps at
+ * most 64 such graphs and releases the least recently used one first.  Each
+ * graph holds its own descriptors and staged workspace within the budget.
+ * gf2x_plan_create records a batch without the per-call check.
  * count == 0 is a no-op.
  * A stream under capture is refused with GF2X_ENOTSUP: the call orders the
  * context's workspace with the context's event and writes descriptors to
@@ -138,6 +142,31 @@ int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_
 int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count,
                      uint64_t *c_base, const uint64_t *a_base, const uint64_t *b_base,
                      uint32_t flags, gf2x_stream_t stream);
+
+/* ------------------------------------------------------------------ plans
+ * A batch recorded once and replayed many times with constant host work.
+ * gf2x_plan_create validates the host items (as gf2x_mul_batched does), groups
+ * them by size class, copies the descriptors to device memory owned by the
+ * plan (synchronously), allocates the plan's staged workspace, and records the
+ * launch sequence (the same kernels as gf2x_mul_batched) in a HIP graph.  Its
+ * device memory counts against the context's budget until the plan is
+ * destroyed.  The items array may be freed or reused after the call; the
+ * base pointers are baked into the plan and must stay valid while it is used.
+ * flags must be 0.  count == 0 gives a plan that launches nothing.
+ * Errors: GF2X_EINVAL, GF2X_ENOMEM, GF2X_EDEVICE. */
+typedef struct gf2x_plan gf2x_plan;
+int gf2x_plan_create(gf2x_plan **out, gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint64_t *c_base,
+                     const uint64_t *a_base, const uint64_t *b_base, uint32_t flags);
+
+/* Enqueue one replay of the plan on `stream`: one graph launch and one event
+ * record, independent of the number of items.  Replays on different streams
+ * must not overlap (they share the plan's workspace).
+ * Errors: GF2X_EINVAL, GF2X_EDEVICE. */
+int gf2x_plan_launch(gf2x_plan *plan, gf2x_stream_t stream);
+
+/* Wait for the plan's last replay, then free it and return its device memory
+ * to the context's budget.  NULL is accepted.  The context must outlive it. */
+void gf2x_plan_destroy(gf2x_plan *plan);
 
 /* Schedule the library uses for n: the padded operand size in 32-bit words,
  * the number of 32x32-bit word products computed by the base case, the

@@ -149,11 +149,21 @@ int ensure_items(gf2x_ctx *ctx, size_t count) {
     return GF2X_OK;
 }
 
+// Change detector for the host descriptors behind a cached graph: a
+// multiply-rotate mix over their 64-bit words in four independent lanes (not
+// cryptographic; it only has to notice an edited descriptor array).
 uint64_t checksum(const gf2x_item *items, uint32_t count) {
-    uint64_t h = 1469598103934665603ull;
     const unsigned char *p = reinterpret_cast<const unsigned char *>(items);
-    for (size_t i = 0; i < (size_t)count * sizeof(gf2x_item); ++i) h = (h ^ p[i]) * 1099511628211ull;
-    return h;
+    const size_t nw = (size_t)count * sizeof(gf2x_item) / 8;  // 4 words per item
+    uint64_t h[4] = {0x9E3779B97F4A7C15ull ^ count, 0xC2B2AE3D27D4EB4Full, 0x165667B19E3779F9ull, 0x27D4EB2F165667C5ull};
+    for (size_t i = 0; i < nw; ++i) {
+        uint64_t w;
+        std::memcpy(&w, p + 8 * i, 8);
+        uint64_t &x = h[i & 3];
+        x ^= w * 0xC2B2AE3D27D4EB4Full;
+        x = ((x << 29) | (x >> 35)) * 0x9E3779B97F4A7C15ull;
+    }
+    return h[0] ^ ((h[1] << 16) | (h[1] >> 48)) ^ ((h[2] << 32) | (h[2] >> 32)) ^ ((h[3] << 48) | (h[3] >> 16));
 }
 
 // Host descriptors -> validated DevItems grouped by class, classes ordered
@@ -265,6 +275,73 @@ int launch_groups(gf2x_ctx *ctx, const DevItem *d_items, const std::vector<Group
         HIP_TRY(hipEventRecord(ctx->fork_event[k], ctx->fork_stream[k]));
         HIP_TRY(hipStreamWaitEvent(s, ctx->fork_event[k], 0));
     }
+    return GF2X_OK;
+}
+
+// Release a recorded batch: wait for its last launch, then free its graph,
+// descriptors and workspace and return their bytes to the budget.
+void release_entry(gf2x_ctx *ctx, GraphEntry &g) {
+    if (g.done && g.launched) hipEventSynchronize(g.done);
+    if (g.exec) hipGraphExecDestroy(g.exec);
+    if (g.graph) hipGraphDestroy(g.graph);
+    if (g.items) hipFree(g.items);
+    if (g.staged_ws) hipFree(g.staged_ws);
+    if (g.done) hipEventDestroy(g.done);
+    ctx->allocated -= g.bytes;
+    g = GraphEntry{};
+}
+
+// Record the launch sequence of a validated batch (host descriptors `host`,
+// class groups `groups`) into g: private descriptor and workspace buffers
+// within the budget, the launches captured on a private stream.  The
+// descriptors are copied on copy_stream (ordered before the first replay on
+// that stream), or synchronously when copy_stream is null.
+int record_graph(gf2x_ctx *ctx, const std::vector<DevItem> &host, std::vector<Group> &groups, uint64_t *c_base,
+                 const uint64_t *a_base, const uint64_t *b_base, GraphEntry &g, hipStream_t copy_stream,
+                 bool use_copy_stream) {
+    g = GraphEntry{};
+    fit_staged(ctx, groups, 0);
+    const size_t sb = staged_bytes(groups);
+    const size_t ib = (host.size() * sizeof(DevItem) + 255) / 256 * 256;
+    if (ctx->allocated + sb + ib > ctx->budget) return GF2X_ENOMEM;
+    if (hipMalloc(&g.items, ib) != hipSuccess) {
+        g.items = nullptr;
+        return GF2X_ENOMEM;
+    }
+    if (sb && hipMalloc(&g.staged_ws, sb) != hipSuccess) {
+        g.staged_ws = nullptr;
+        hipFree(g.items);
+        g.items = nullptr;
+        return GF2X_ENOMEM;
+    }
+    g.bytes = ib + sb;
+    ctx->allocated += g.bytes;
+    hipError_t e = use_copy_stream
+                       ? hipMemcpyAsync(g.items, host.data(), host.size() * sizeof(DevItem), hipMemcpyHostToDevice,
+                                        copy_stream)
+                       : hipMemcpy(g.items, host.data(), host.size() * sizeof(DevItem), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&g.done, hipEventDisableTiming);
+    hipStream_t cap = nullptr;
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        int lrc = launch_groups(ctx, g.items, groups, c_base, a_base, b_base, g.staged_ws, cap);
+        hipError_t e2 = hipStreamEndCapture(cap, &g.graph);
+        e = lrc ? hipErrorLaunchFailure : e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    if (cap) hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        release_entry(ctx, g);
+        return device_error(e);
+    }
+    return GF2X_OK;
+}
+
+int replay(GraphEntry &g, hipStream_t s) {
+    HIP_TRY(hipGraphLaunch(g.exec, s));
+    HIP_TRY(hipEventRecord(g.done, s));
+    g.launched = true;
     return GF2X_OK;
 }
 
@@ -407,12 +484,7 @@ int gf2x_create(gf2x_ctx **out, const gf2x_opts *opts) {
 void gf2x_destroy(gf2x_ctx *ctx) {
     if (!ctx) return;
     hipSetDevice(ctx->device);
-    for (auto &kv : ctx->graphs) {
-        if (kv.second.exec) hipGraphExecDestroy(kv.second.exec);
-        if (kv.second.graph) hipGraphDestroy(kv.second.graph);
-        if (kv.second.items) hipFree(kv.second.items);
-        if (kv.second.staged_ws) hipFree(kv.second.staged_ws);
-    }
+    for (auto &kv : ctx->graphs) release_entry(ctx, kv.second);
     if (ctx->staged_ws) hipFree(ctx->staged_ws);
     if (ctx->inv_ws) hipFree(ctx->inv_ws);
     toeplitz::release(ctx->tz);
@@ -496,67 +568,53 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
             return rc;
         }
     }
-    std::vector<DevItem> host;
-    std::vector<Group> groups;
-    int rc = build_items(ctx, items, count, host, groups);
-    if (rc) return rc;
-
     if (flags & GF2X_USE_GRAPH) {
+        // A cache hit costs one pass over the descriptor words (the change
+        // check) and the replay; validation and grouping ran when the entry
+        // was recorded.
         auto key = std::make_tuple((const void *)items, count, (const void *)c_base, (const void *)a_base,
                                    (const void *)b_base, flags, (void *)s);
         const uint64_t sum = checksum(items, count);
         auto it = ctx->graphs.find(key);
-        if (it != ctx->graphs.end() && it->second.checksum != sum) {
-            HIP_TRY(hipStreamSynchronize(s));  // the old graph may still be running on s
-            hipGraphExecDestroy(it->second.exec);
-            hipGraphDestroy(it->second.graph);
-            hipFree(it->second.items);
-            if (it->second.staged_ws) {
-                hipFree(it->second.staged_ws);
-                ctx->allocated -= it->second.staged_bytes;
-            }
+        if (it != ctx->graphs.end() && it->second.checksum == sum) {
+            it->second.last_use = ++ctx->graph_clock;
+            return replay(it->second, s);
+        }
+        if (it != ctx->graphs.end()) {  // the descriptors changed: record again
+            release_entry(ctx, it->second);
             ctx->graphs.erase(it);
-            it = ctx->graphs.end();
         }
-        if (it == ctx->graphs.end()) {
-            GraphEntry g;
-            g.checksum = sum;
-            fit_staged(ctx, groups, 0);
-            const size_t sb = staged_bytes(groups);
-            if (sb) {
-                if (hipMalloc(&g.staged_ws, sb) != hipSuccess) return GF2X_ENOMEM;
-                g.staged_bytes = sb;
-                ctx->allocated += sb;
-            }
-            if (hipMalloc(&g.items, count * sizeof(DevItem)) != hipSuccess) return GF2X_ENOMEM;
-            HIP_TRY(hipMemcpyAsync(g.items, host.data(), count * sizeof(DevItem), hipMemcpyHostToDevice, s));
-            // capture the launches on a private stream, ordered after the copy
-            hipStream_t cap;
-            HIP_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
-            hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                int lrc = launch_groups(ctx, g.items, groups, c_base, a_base, b_base, g.staged_ws, cap);
-                hipError_t e2 = hipStreamEndCapture(cap, &g.graph);
-                if (lrc) e = hipErrorLaunchFailure;
-                else e = e2;
-            }
-            if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
-            hipStreamDestroy(cap);
-            if (e != hipSuccess) {
-                if (g.graph) hipGraphDestroy(g.graph);
-                hipFree(g.items);
-                if (g.staged_ws) {
-                    hipFree(g.staged_ws);
-                    ctx->allocated -= g.staged_bytes;
-                }
-                return device_error(e);
-            }
-            it = ctx->graphs.emplace(key, g).first;
+        std::vector<DevItem> host;
+        std::vector<Group> groups;
+        int rc = build_items(ctx, items, count, host, groups);
+        if (rc) return rc;
+        while (ctx->graphs.size() >= gf2x_ctx::kMaxGraphs) {
+            auto lru = ctx->graphs.begin();
+            for (auto j = ctx->graphs.begin(); j != ctx->graphs.end(); ++j)
+                if (j->second.last_use < lru->second.last_use) lru = j;
+            release_entry(ctx, lru->second);
+            ctx->graphs.erase(lru);
         }
-        HIP_TRY(hipGraphLaunch(it->second.exec, s));
-        return GF2X_OK;
+        GraphEntry g;
+        rc = record_graph(ctx, host, groups, c_base, a_base, b_base, g, s, true);
+        if (rc == GF2X_ENOMEM && !ctx->graphs.empty()) {
+            // release the cached entries (their budget) and try once more
+            for (auto &kv : ctx->graphs) release_entry(ctx, kv.second);
+            ctx->graphs.clear();
+            rc = build_items(ctx, items, count, host, groups);
+            if (rc == GF2X_OK) rc = record_graph(ctx, host, groups, c_base, a_base, b_base, g, s, true);
+        }
+        if (rc) return rc;
+        g.checksum = sum;
+        g.last_use = ++ctx->graph_clock;
+        it = ctx->graphs.emplace(key, g).first;
+        return replay(it->second, s);
     }
 
+    std::vector<DevItem> host;
+    std::vector<Group> groups;
+    int rc = build_items(ctx, items, count, host, groups);
+    if (rc) return rc;
     rc = ensure_items(ctx, count);
     if (rc) return rc;
     fit_staged(ctx, groups, ctx->staged_ws_bytes);
@@ -569,6 +627,45 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
     HIP_TRY(hipEventRecord(ctx->ws_free, s));
     ctx->ws_used = true;
     return GF2X_OK;
+}
+
+int gf2x_plan_create(gf2x_plan **out, gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint64_t *c_base,
+                     const uint64_t *a_base, const uint64_t *b_base, uint32_t flags) {
+    if (!out) return GF2X_EINVAL;
+    *out = nullptr;
+    if (!ctx || flags != 0) return GF2X_EINVAL;
+    if (count && (!items || !c_base || !a_base || !b_base)) return GF2X_EINVAL;
+    if (!aligned8(c_base) || !aligned8(a_base) || !aligned8(b_base)) return GF2X_EINVAL;
+    HIP_TRY(hipSetDevice(ctx->device));
+    gf2x_plan *plan = new (std::nothrow) gf2x_plan();
+    if (!plan) return GF2X_ENOMEM;
+    plan->ctx = ctx;
+    if (count) {
+        std::vector<DevItem> host;
+        std::vector<Group> groups;
+        int rc = build_items(ctx, items, count, host, groups);
+        if (rc == GF2X_OK) rc = record_graph(ctx, host, groups, c_base, a_base, b_base, plan->g, nullptr, false);
+        if (rc) {
+            delete plan;
+            return rc;
+        }
+    }
+    *out = plan;
+    return GF2X_OK;
+}
+
+int gf2x_plan_launch(gf2x_plan *plan, gf2x_stream_t stream) {
+    if (!plan) return GF2X_EINVAL;
+    if (!plan->g.exec) return GF2X_OK;  // empty batch
+    HIP_TRY(hipSetDevice(plan->ctx->device));
+    return replay(plan->g, reinterpret_cast<hipStream_t>(stream));
+}
+
+void gf2x_plan_destroy(gf2x_plan *plan) {
+    if (!plan) return;
+    hipSetDevice(plan->ctx->device);
+    release_entry(plan->ctx, plan->g);
+    delete plan;
 }
 
 // Inversion by exponentiation (the Itoh-Tsujii addition chain): for an odd

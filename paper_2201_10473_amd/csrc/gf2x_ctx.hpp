@@ -14,16 +14,28 @@
 
 namespace gf2x {
 
+// A recorded launch sequence of one batch: its graph, the private copy of
+// the descriptors and the private workspace of its staged groups.  `done`
+// is recorded after every launch, so the entry can be released safely.
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     DevItem *items = nullptr;  // private copy of the descriptors
     void *staged_ws = nullptr; // private workspace of the staged groups
-    size_t staged_bytes = 0;
+    size_t bytes = 0;          // device bytes of items + staged_ws (counted in the budget)
+    hipEvent_t done = nullptr;
+    bool launched = false;
     uint64_t checksum = 0;
+    uint64_t last_use = 0;
 };
 
 }  // namespace gf2x
+
+// A batch recorded once by gf2x_plan_create and replayed by gf2x_plan_launch.
+struct gf2x_plan {
+    gf2x_ctx *ctx = nullptr;
+    gf2x::GraphEntry g;
+};
 
 struct gf2x_ctx {
     int device = 0;
@@ -44,9 +56,14 @@ struct gf2x_ctx {
     void *inv_ws = nullptr;        // working buffers of gf2x_inv_cyclic_batched (same guard)
     size_t inv_ws_bytes = 0;
     bool ws_used = false;
+    // GF2X_USE_GRAPH cache, keyed by (items, count, bases, flags, stream);
+    // at most kMaxGraphs entries, the least recently used one is released
+    // first.
+    static constexpr size_t kMaxGraphs = 64;
     std::map<std::tuple<const void *, uint32_t, const void *, const void *, const void *, uint32_t, void *>,
              gf2x::GraphEntry>
         graphs;
+    uint64_t graph_clock = 0;
     gf2x::toeplitz::Workspace tz;
     std::map<uint32_t, int> tuned;         // w32 -> class chosen by gf2x_tune or the cache file
     std::map<uint32_t, int> tuned_direct;  // w32 -> fastest direct class measured for that size

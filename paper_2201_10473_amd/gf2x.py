@@ -120,6 +120,12 @@ def load():
         fn.restype = ctypes.c_int
     lib.gf2x_mul_batched.argtypes = [vp, vp, u32, vp, vp, vp, u32, vp]
     lib.gf2x_mul_batched.restype = ctypes.c_int
+    lib.gf2x_plan_create.argtypes = [ctypes.POINTER(vp), vp, vp, u32, vp, vp, vp, u32]
+    lib.gf2x_plan_create.restype = ctypes.c_int
+    lib.gf2x_plan_launch.argtypes = [vp, vp]
+    lib.gf2x_plan_launch.restype = ctypes.c_int
+    lib.gf2x_plan_destroy.argtypes = [vp]
+    lib.gf2x_plan_destroy.restype = None
     lib.gf2x_inv_cyclic_batched.argtypes = [vp, vp, u32, vp, vp, u32, vp]
     lib.gf2x_inv_cyclic_batched.restype = ctypes.c_int
     lib.gf2x_schedule_info.argtypes = [
@@ -242,6 +248,10 @@ class Context:
             "gf2x_mul_batched",
         )
 
+    def plan(self, items, c_base, a_base, b_base):
+        """Record a batch (host items) once for replays with constant host work."""
+        return Plan(self, items, c_base, a_base, b_base)
+
     def inv_cyclic_batched(self, items, c_base, a_base, stream=None):
         """Inverses in F2[X]/(X^n - 1) (n an odd prime; all items of one n) of
         the items' operands a_base + a_off, written at c_base + c_off.  For an
@@ -276,6 +286,42 @@ class Context:
             "gf2x_schedule_info",
         )
         return s.value, base.value, ops.value, name.value.decode()
+
+
+class Plan:
+    """A recorded batch (gf2x_plan_* in the C ABI); launch() replays it."""
+
+    def __init__(self, ctx, items, c_base, a_base, b_base):
+        self._lib = load()
+        self._ctx = ctx
+        items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
+        h = ctypes.c_void_p()
+        _check(
+            self._lib.gf2x_plan_create(ctypes.byref(h), ctx._h, items.ctypes.data, len(items), _ptr(c_base),
+                                       _ptr(a_base), _ptr(b_base), 0),
+            "gf2x_plan_create",
+        )
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(self._lib.gf2x_plan_launch(self._h, _stream(stream)), "gf2x_plan_launch")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.gf2x_plan_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

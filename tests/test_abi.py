@@ -81,3 +81,14 @@ def test_server_rejects_null_context():
     assert lib.gf2x_srv_drain(None, 1) == gf2x.GF2X_EINVAL
     assert lib.gf2x_srv_now_ns() > 0
     lib.gf2x_srv_destroy(None)
+
+
+def test_plan_entry_points_reject_null_arguments():
+    lib = gf2x.load()
+    p = 4096  # never dereferenced: the checks fail first
+    assert lib.gf2x_plan_create(None, None, p, 1, p, p, p, 0) == gf2x.GF2X_EINVAL
+    out = ctypes.c_void_p()
+    assert lib.gf2x_plan_create(ctypes.byref(out), None, p, 1, p, p, p, 0) == gf2x.GF2X_EINVAL
+    assert out.value is None
+    assert lib.gf2x_plan_launch(None, None) == gf2x.GF2X_EINVAL
+    lib.gf2x_plan_destroy(None)
