@@ -143,6 +143,26 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count,
                      uint64_t *c_base, const uint64_t *a_base, const uint64_t *b_base,
                      uint32_t flags, gf2x_stream_t stream);
 
+/* For callers that cannot allocate device memory (tight serving loops, code
+ * that must not call hipMalloc): gf2x_mul_batched with host items, without
+ * any allocation.  The descriptors and the staged workspace of the call live
+ * in a static device array of GF2X_NOALLOC_SCRATCH_BYTES per device (held
+ * until the process ends): descriptors of at most GF2X_NOALLOC_MAX_ITEMS
+ * items (2.5 MiB), the rest of the array as workspace; a size class whose staged workspace does not fit runs its
+ * one-workgroup form (same result).  Items, operands and results are those
+ * of gf2x_mul_batched without flags (ring and full kinds, mixed sizes); the
+ * class groups run one after another on `stream`, and the descriptors are
+ * copied from `items` during the call.  Every call on a device shares
+ * that device's array and overwrites it: calls that overlap on one device
+ * (different streams, or other host threads) race; calls ordered on one
+ * stream are safe.  A stream under capture is refused (GF2X_ENOTSUP).
+ * Errors: GF2X_EINVAL, GF2X_ENOMEM (count above GF2X_NOALLOC_MAX_ITEMS),
+ * GF2X_EDEVICE, GF2X_ENOTSUP. */
+#define GF2X_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define GF2X_NOALLOC_MAX_ITEMS 65536u
+int gf2x_mul_batched_noalloc(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint64_t *c_base,
+                             const uint64_t *a_base, const uint64_t *b_base, gf2x_stream_t stream);
+
 /* ------------------------------------------------------------------ plans
  * A batch recorded once and replayed many times with constant host work.
  * gf2x_plan_create validates the host items (as gf2x_mul_batched does), groups

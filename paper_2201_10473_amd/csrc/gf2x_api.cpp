@@ -463,6 +463,8 @@ int gf2x_create(gf2x_ctx **out, const gf2x_opts *opts) {
     hipDeviceProp_t prop;
     hipError_t e = hipGetDeviceProperties(&prop, o.device);
     if (e == hipSuccess) e = prepare_kernels();
+    // this device's copy of the allocation-free scratch array (device current)
+    if (e == hipSuccess) e = scratch_for_device(o.device, &ctx->scratch);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->ws_free, hipEventDisableTiming);
     if (e != hipSuccess) {
         delete ctx;
@@ -626,6 +628,44 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
     if (rc) return rc;
     HIP_TRY(hipEventRecord(ctx->ws_free, s));
     ctx->ws_used = true;
+    return GF2X_OK;
+}
+
+// The batch of gf2x_mul_batched (host items) in the static scratch array of
+// the context's device: descriptors and staged workspace, no allocation.
+// Groups run one after another on the caller's stream; a staged group whose
+// workspace does not fit the scratch that is left runs its direct class.
+int gf2x_mul_batched_noalloc(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint64_t *c_base,
+                             const uint64_t *a_base, const uint64_t *b_base, gf2x_stream_t stream) {
+    if (!ctx) return GF2X_EINVAL;
+    if (count == 0) return GF2X_OK;
+    if (!items || !c_base || !a_base || !b_base) return GF2X_EINVAL;
+    if (!aligned8(c_base) || !aligned8(a_base) || !aligned8(b_base)) return GF2X_EINVAL;
+    if (count > kScratchMaxItems) return GF2X_ENOMEM;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    HIP_TRY(hipSetDevice(ctx->device));
+    if (int rc = refuse_capture(s)) return rc;
+    thread_local std::vector<DevItem> host;
+    thread_local std::vector<Group> groups;
+    int rc = build_items(ctx, items, count, host, groups);
+    if (rc) return rc;
+    const size_t cap = kScratchBytes - kScratchItemBytes;
+    size_t total = staged_bytes(groups);
+    for (Group &g : groups) {
+        if (total <= cap) break;
+        if (class_info(g.cls).child >= 0) {
+            total -= (staged_workspace_bytes(g.cls, g.count) + 255) / 256 * 256;
+            g.cls = class_info(g.cls).direct;
+        }
+    }
+    char *base = reinterpret_cast<char *>(ctx->scratch);
+    DevItem *desc = reinterpret_cast<DevItem *>(base);
+    HIP_TRY(hipMemcpyAsync(desc, host.data(), (size_t)count * sizeof(DevItem), hipMemcpyHostToDevice, s));
+    char *wp = base + kScratchItemBytes;
+    for (const Group &g : groups) {
+        rc = launch_one(ctx, g, desc, wp, c_base, a_base, b_base, s);
+        if (rc) return rc;
+    }
     return GF2X_OK;
 }
 

@@ -40,6 +40,7 @@ struct gf2x_plan {
 struct gf2x_ctx {
     int device = 0;
     int num_cu = 0;
+    void *scratch = nullptr;  // this device's copy of the allocation-free scratch array
     size_t budget = 0;
     size_t allocated = 0;
     int cls_of_w32[gf2x::kMaxWords32 + 1];     // batch schedule per size (direct or staged)

@@ -38,6 +38,19 @@ struct ClassInfo {
     int points;              // staged: point products per item (5 or 7); else 0
 };
 
+// Scratch of the allocation-free batched entry point (a static device array
+// per device): descriptors of up to kScratchMaxItems items, then the staged
+// workspace.
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr uint32_t kScratchMaxItems = 65536;
+constexpr size_t kScratchItemBytes = (size_t)kScratchMaxItems * sizeof(DevItem);
+static_assert(kScratchItemBytes % 256 == 0, "workspace region starts 256-byte aligned");
+static_assert(kScratchBytes == GF2X_NOALLOC_SCRATCH_BYTES && kScratchMaxItems == GF2X_NOALLOC_MAX_ITEMS,
+              "scratch limits as declared in gf2x.h");
+// Address of the current device's copy of the scratch array (looked up once
+// per device; call with that device current).
+hipError_t scratch_for_device(int device, void **ptr);
+
 const ClassInfo &class_info(int cls);
 hipError_t prepare_kernels();
 // Staged classes need a device workspace: bytes for `count` products.

@@ -48,6 +48,8 @@ template <class T, int CHILD>
 static hipError_t staged_impl(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
                               const uint64_t *b_base, void *ws, int num_cu, hipStream_t s) {
     constexpr int S1 = T::S1, NP = T::NP;
+    // point operand b sits S1 / 2 uint64 words after a (k_child_items)
+    static_assert(S1 % 2 == 0, "child operands start on a uint64 word");
     const size_t in_bytes = ((size_t)count * 2 * NP * S1 * 4 + 255) / 256 * 256;
     u32 *ws_in = reinterpret_cast<u32 *>(ws);
     u32 *ws_out = reinterpret_cast<u32 *>(reinterpret_cast<char *>(ws) + in_bytes);

@@ -46,6 +46,32 @@ __global__ void k_fill_words(uint64_t *dst, size_t count, uint64_t seed) {
     }
 }
 
+// ------------------------------------------------- allocation-free scratch
+// Device memory of gf2x_mul_batched_noalloc: the descriptors of one call
+// (first kScratchItemBytes) and the workspace of its staged groups (the
+// rest).  Every device the library runs on holds its own copy, loaded with
+// the code object, until the process ends.  Host code never passes this name
+// to a kernel: it uses the per-device address from scratch_for_device.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+hipError_t scratch_for_device(int device, void **ptr) {
+    static std::mutex mu;
+    static std::map<int, void *> addr;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = addr.find(device);
+    if (it != addr.end()) {
+        *ptr = it->second;
+        return hipSuccess;
+    }
+    // with `device` current: the address of this device's copy of the array
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = p;
+    *ptr = p;
+    return hipSuccess;
+}
+
 // ------------------------------------------------------------ host side
 #define GF2X_INFO(id, name, T) \
     {id, name, T::S, lds_words<T>() * 4, T::BASE, T::OPS, -1, id, 0},

@@ -120,6 +120,8 @@ def load():
         fn.restype = ctypes.c_int
     lib.gf2x_mul_batched.argtypes = [vp, vp, u32, vp, vp, vp, u32, vp]
     lib.gf2x_mul_batched.restype = ctypes.c_int
+    lib.gf2x_mul_batched_noalloc.argtypes = [vp, vp, u32, vp, vp, vp, vp]
+    lib.gf2x_mul_batched_noalloc.restype = ctypes.c_int
     lib.gf2x_plan_create.argtypes = [ctypes.POINTER(vp), vp, vp, u32, vp, vp, vp, u32]
     lib.gf2x_plan_create.restype = ctypes.c_int
     lib.gf2x_plan_launch.argtypes = [vp, vp]
@@ -246,6 +248,17 @@ class Context:
                 _stream(stream),
             ),
             "gf2x_mul_batched",
+        )
+
+    def mul_batched_noalloc(self, items, c_base, a_base, b_base, stream=None):
+        """mul_batched with host items, using the library's static scratch
+        array instead of allocated workspace (no device allocation)."""
+        items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
+        _check(
+            self._lib.gf2x_mul_batched_noalloc(
+                self._h, items.ctypes.data, len(items), _ptr(c_base), _ptr(a_base), _ptr(b_base), _stream(stream)
+            ),
+            "gf2x_mul_batched_noalloc",
         )
 
     def plan(self, items, c_base, a_base, b_base):
