@@ -180,6 +180,109 @@ def time_mixed(ctx, steps, seed, count=8192):
             "valu_frac": round(ops / (ms * 1e-3) / VALU_PEAK, 4)}
 
 
+def _plan_ms(ctx, items, dC, dA, dB, steps):
+    """Mean device time of one replay of a recorded batch (HIP events on the
+    launch stream), after at least 0.3 s of warm-up replays."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    with ctx.plan(items, dC, dA, dB) as plan:
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < 0.3:
+            plan.launch(stream)
+            torch.cuda.synchronize()
+        s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s_ev.record(stream)
+        for _ in range(steps):
+            plan.launch(stream)
+        e_ev.record(stream)
+        torch.cuda.synchronize()
+    return s_ev.elapsed_time(e_ev) / steps
+
+
+def time_sparse(ctx, steps, seed, count=4096):
+    """Dense x sparse ring products at each ring size (weights of the mixed
+    workload), through the constant-time rotation barrel (sparse kind, the
+    positions as input) and through the dense path (the sparse operand as a
+    dense polynomial); both checked equal on every item."""
+    import numpy as np
+    import torch
+
+    from paper_2201_10473_amd import gf2x, inputs
+
+    out = {}
+    for n in inputs.RING_SIZES:
+        w = inputs.sparse_weight_for(n)
+        W = gf2x.words(n)
+        A = inputs.dense_batch(n, count, seed, 0)
+        pos = [inputs.sparse_positions(n, w, seed, i) for i in range(count)]
+        P = np.zeros(count * ((w + 1) // 2), dtype=np.uint64)
+        P.view(np.uint32).reshape(count, -1)[:, :w] = np.asarray(pos, dtype=np.uint32)
+        S = np.stack([inputs.from_positions(n, p) for p in pos])
+        off = np.arange(count, dtype=np.uint64) * W
+        poff = np.arange(count, dtype=np.uint64) * ((w + 1) // 2)
+        sp_items = gf2x.make_items(n, gf2x.sparse_kind(w), off, poff, off)
+        de_items = gf2x.make_items(n, gf2x.KIND_CYCLIC, off, off, off)
+        dA = torch.from_numpy(A.ravel().view(np.int64)).cuda()
+        dP = torch.from_numpy(P.view(np.int64)).cuda()
+        dS = torch.from_numpy(S.ravel().view(np.int64)).cuda()
+        dC1 = torch.zeros(count * W, dtype=torch.int64, device="cuda")
+        dC2 = torch.zeros(count * W, dtype=torch.int64, device="cuda")
+        ms_sp = _plan_ms(ctx, sp_items, dC1, dA, dP, steps)
+        ms_de = _plan_ms(ctx, de_items, dC2, dA, dS, steps)
+        if not torch.equal(dC1, dC2):
+            raise AssertionError("sparse and dense paths disagree at n=%d" % n)
+        out[str(n)] = {"weight": w, "batch": count, "sparse_ms": round(ms_sp, 4), "dense_ms": round(ms_de, 4),
+                       "sparse_products_per_s": round(count / (ms_sp * 1e-3), 1),
+                       "dense_products_per_s": round(count / (ms_de * 1e-3), 1),
+                       "sparse_over_dense": round(ms_de / ms_sp, 3)}
+        log("  n=%d w=%d: sparse %.3f ms, dense %.3f ms per %d products" % (n, w, ms_sp, ms_de, count))
+    return out
+
+
+def time_mixed_sparse(ctx, steps, seed, count=8192):
+    """The mixed workload with its dense x sparse half given as positions
+    (sparse kind): one recorded plan, every result equal to the same
+    workload computed with the sparse operands as dense polynomials."""
+    import numpy as np
+    import torch
+
+    from paper_2201_10473_amd import gf2x, inputs, serve
+
+    ns, off, A, B = serve.make_requests(count, seed)
+    pos_words, pos_off, sp_kind = [], [], []
+    total = len(B)
+    for i in range(1, count, 2):
+        n = int(ns[i])
+        w = inputs.sparse_weight_for(n)
+        p = inputs.sparse_positions(n, w, seed, i)
+        W = (n + 63) // 64
+        B[int(off[i]):int(off[i]) + W] = inputs.from_positions(n, p)
+        words = np.zeros((w + 1) // 2, dtype=np.uint64)
+        words.view(np.uint32)[:w] = np.asarray(p, dtype=np.uint32)
+        pos_words.append(words)
+        pos_off.append(total)
+        total += len(words)
+        sp_kind.append(gf2x.sparse_kind(w))
+    Bs = np.concatenate([B] + pos_words)
+    kinds = np.zeros(count, dtype=np.uint32)
+    kinds[1::2] = sp_kind
+    b_off = off.copy()
+    b_off[1::2] = pos_off
+    items_sp = gf2x.make_items(ns, kinds, off, b_off, off)
+    items_de = gf2x.make_items(ns, gf2x.KIND_CYCLIC, off, off, off)
+    dA = torch.from_numpy(A.view(np.int64)).cuda()
+    dB = torch.from_numpy(Bs.view(np.int64)).cuda()
+    dC1 = torch.zeros(len(A), dtype=torch.int64, device="cuda")
+    dC2 = torch.zeros(len(A), dtype=torch.int64, device="cuda")
+    ms_sp = _plan_ms(ctx, items_sp, dC1, dA, dB, steps)
+    ms_de = _plan_ms(ctx, items_de, dC2, dA, dB, steps)
+    if not torch.equal(dC1, dC2):
+        raise AssertionError("mixed workload: sparse-kind and dense results differ")
+    return {"products": count, "ms_per_launch": round(ms_sp, 4), "products_per_s": round(count / (ms_sp * 1e-3), 1),
+            "dense_path_ms_per_launch": round(ms_de, 4), "speedup_over_dense_path": round(ms_de / ms_sp, 3)}
+
+
 def single_latency(ctx, n, calls, warmup, seed):
     """One product per call, each call synchronized: median device time (HIP
     events) and median host round trip, after `warmup` untimed calls."""
@@ -524,6 +627,8 @@ def main():
             log("  packed %.3f ms, toeplitz %.3f ms" % (ms_p, ms_t))
 
     mixed = None
+    sparse = None
+    mixed_sparse = None
     serving = []
     trace = None
     single = None
@@ -535,6 +640,11 @@ def main():
         log("mixed workload: 8192 products, six sizes, half dense x sparse")
         mixed = time_mixed(ctx, 10, inputs.SEED_BASE + 4)
         log("  %s" % mixed)
+        log("dense x sparse: constant-time rotation barrel vs the dense path, 4096 products per size")
+        sparse = time_sparse(ctx, 10, inputs.SEED_BASE + 14)
+        log("mixed workload with the sparse half as positions (sparse kind)")
+        mixed_sparse = time_mixed_sparse(ctx, 10, inputs.SEED_BASE + 4)
+        log("  %s" % mixed_sparse)
         log("inverses in F2[X]/(X^12323 - 1): one, and a batch of 1024")
         inverse = time_inverse(ctx, 12323, inputs.SEED_BASE + 9)
         log("  %s" % inverse)
@@ -599,6 +709,8 @@ def main():
             single_product=single,
             inverse=inverse,
             mixed=mixed,
+            mixed_sparse_kind=mixed_sparse,
+            sparse=sparse,
             serving=serving,
             hqc_trace=trace,
         ),

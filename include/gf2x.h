@@ -64,6 +64,17 @@ typedef struct ihipStream_t *gf2x_stream_t;
 /* Item kinds for gf2x_mul_batched. */
 #define GF2X_KIND_CYCLIC 0u /* c: W(n) words, c = a*b mod (X^n - 1) */
 #define GF2X_KIND_FULL 1u   /* c: 2*W(n) words, c = a*b in F2[X]    */
+/* Dense x sparse ring product (Section 1: the sparse-dense products of the
+ * code-based KEMs), constant time in the positions: c (W(n) words) =
+ * a * (X^p_1 + ... + X^p_w) mod (X^n - 1), where the w positions are uint32
+ * values at b_base + b_off (read as uint32 words from that uint64 offset),
+ * each taken modulo n (equal positions cancel, as in F2).  The weight w is
+ * public and is carried in the kind: GF2X_SPARSE_KIND(w), 0 <= w < 2^24.
+ * n <= GF2X_SPARSE_MAX_BITS.  Host items only (device-resident descriptors
+ * of this kind are skipped). */
+#define GF2X_KIND_SPARSE 2u
+#define GF2X_SPARSE_KIND(w) (GF2X_KIND_SPARSE | ((uint32_t)(w) << 8))
+#define GF2X_SPARSE_MAX_BITS 65504u
 
 /* Flags for gf2x_mul_batched. */
 #define GF2X_ITEMS_ON_DEVICE 0x1u  /* `items` is a device pointer (not validated on the host)               */
@@ -85,7 +96,7 @@ typedef struct gf2x_opts {
  * given to gf2x_mul_batched; operands hold W(n_bits) words. */
 typedef struct gf2x_item {
     uint32_t n_bits; /* 1 <= n_bits <= GF2X_MAX_BITS */
-    uint32_t kind;   /* GF2X_KIND_CYCLIC or GF2X_KIND_FULL */
+    uint32_t kind;   /* GF2X_KIND_CYCLIC, GF2X_KIND_FULL or GF2X_SPARSE_KIND(w) */
     uint64_t a_off, b_off, c_off;
 } gf2x_item;
 

@@ -30,6 +30,7 @@ SOURCES = [
     "gf2x_kern_d3.hip",
     "gf2x_kernels.hip",
     "gf2x_toeplitz.hip",
+    "gf2x_sparse.hip",
     "gf2x_inv.hip",
     "gf2x_api.cpp",
     "gf2x_serve.cpp",

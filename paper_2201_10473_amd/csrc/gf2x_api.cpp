@@ -180,8 +180,16 @@ int build_items(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, std::vect
     for (uint32_t i = 0; i < count; ++i) {
         const gf2x_item &it = items[i];
         if (it.n_bits == 0 || it.n_bits > kMaxBits) return GF2X_EINVAL;
-        if (it.kind != GF2X_KIND_CYCLIC && it.kind != GF2X_KIND_FULL) return GF2X_EINVAL;
-        const int cls = ctx->cls_of_w32[(it.n_bits + 31u) / 32u];
+        int cls;
+        if ((it.kind & 0xFFu) == GF2X_KIND_SPARSE) {  // weight in the upper 24 bits
+            const int idx = sparse_class_for(it.n_bits);
+            if (idx < 0) return GF2X_EINVAL;
+            cls = kSparseBase + idx;
+        } else if (it.kind == GF2X_KIND_CYCLIC || it.kind == GF2X_KIND_FULL) {
+            cls = ctx->cls_of_w32[(it.n_bits + 31u) / 32u];
+        } else {
+            return GF2X_EINVAL;
+        }
         out[i] = DevItem{it.n_bits, it.kind, (uint32_t)cls, 0u, it.a_off, it.b_off, it.c_off};
     }
     std::stable_sort(out.begin(), out.end(), [](const DevItem &x, const DevItem &y) {

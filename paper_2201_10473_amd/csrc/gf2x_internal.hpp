@@ -14,6 +14,11 @@ constexpr int kNumDirect = 25;   // classes computed inside one workgroup
 constexpr int kNumClasses = 34;  // plus the staged classes
 constexpr uint32_t kKindCyclic = 0;
 constexpr uint32_t kKindFull = 1;
+constexpr uint32_t kKindSparse = 2;  // low byte of the kind; the weight is kind >> 8
+static_assert(kKindSparse == GF2X_KIND_SPARSE, "kind code as declared in gf2x.h");
+// Size classes of dense x sparse products get the ids kSparseBase + index.
+constexpr int kSparseBase = 64;
+inline bool is_sparse_class(int cls) { return cls >= kSparseBase; }
 constexpr uint32_t kMaxBits = 131072;
 constexpr uint32_t kMaxWords32 = kMaxBits / 32;
 
@@ -52,6 +57,15 @@ static_assert(kScratchBytes == GF2X_NOALLOC_SCRATCH_BYTES && kScratchMaxItems ==
 hipError_t scratch_for_device(int device, void **ptr);
 
 const ClassInfo &class_info(int cls);
+
+// Dense x sparse products (gf2x_sparse.hip): the sparse size class of n
+// (index into the class list, -1 if n is too large), its words per lane,
+// and the launcher of a batch of one class.
+int sparse_class_for(uint32_t n);
+int sparse_words_per_lane(int idx);
+hipError_t prepare_sparse_kernels();
+hipError_t launch_sparse(int idx, const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
+                         const uint64_t *b_base, int num_cu, hipStream_t s);
 hipError_t prepare_kernels();
 // Staged classes need a device workspace: bytes for `count` products.
 size_t staged_workspace_bytes(int cls, uint32_t count);

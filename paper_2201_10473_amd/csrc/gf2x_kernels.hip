@@ -99,7 +99,24 @@ static bool init_direct() {
 }
 static const bool kDirectReady = init_direct();
 
-const ClassInfo &class_info(int cls) { return kClassInfo[cls]; }
+// The sparse size classes as class-table rows: S is the largest ceil(n/32)
+// the class holds, lds_bytes one wavefront's buffer; ops and base are not
+// modelled here (the product is not a Karatsuba schedule).
+static ClassInfo kSparseInfo[8];
+static bool init_sparse_info() {
+    static const char *names[8] = {"SP.R8", "SP.R13", "SP.R18", "SP.R25", "SP.R36", "SP.R41", "SP.R57", "SP.R64"};
+    for (int i = 0; i < 8; ++i) {
+        const int R = sparse_words_per_lane(i);
+        kSparseInfo[i] = ClassInfo{kSparseBase + i, names[i], (64 * R - 2) / 2, 256 * R, 0, 0, -1,
+                                   kSparseBase + i, 0};
+    }
+    return true;
+}
+static const bool kSparseInfoReady = init_sparse_info();
+
+const ClassInfo &class_info(int cls) {
+    return is_sparse_class(cls) ? kSparseInfo[cls - kSparseBase] : kClassInfo[cls];
+}
 
 typedef void (*SingleFn)(const uint64_t *, const uint64_t *, uint64_t *, u32, u32);
 typedef void (*BatchedFn)(const DevItem *, u32, uint64_t *, const uint64_t *, const uint64_t *);
@@ -126,7 +143,10 @@ static hipError_t set_lds_limit(const void *fn, int bytes) {
 hipError_t prepare_kernels() {
     (void)kDirectReady;
     (void)kHandlesReady;
+    (void)kSparseInfoReady;
     hipError_t e = prepare_staged_kernels();
+    if (e != hipSuccess) return e;
+    e = prepare_sparse_kernels();
     if (e != hipSuccess) return e;
     for (int c = 0; c < kNumDirect; ++c) {
         e = set_lds_limit(kSingle[c], kClassInfo[c].lds_bytes);
@@ -165,6 +185,7 @@ int occupancy(const void *fn, int lds_bytes) {
 
 hipError_t launch_batched(int cls, const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
                           const uint64_t *b_base, int num_cu, hipStream_t s) {
+    if (is_sparse_class(cls)) return launch_sparse(cls - kSparseBase, items, count, c_base, a_base, b_base, num_cu, s);
     const void *fnp = kBatched[cls];
     const int lds = kClassInfo[cls].lds_bytes;
     const long long cap = (long long)num_cu * occupancy(fnp, lds);
@@ -175,7 +196,7 @@ hipError_t launch_batched(int cls, const DevItem *items, uint32_t count, uint64_
 }
 
 size_t staged_workspace_bytes(int cls, uint32_t count) {
-    const ClassInfo &ci = kClassInfo[cls];
+    const ClassInfo &ci = class_info(cls);
     if (ci.child < 0) return 0;
     const size_t S1 = (size_t)kClassInfo[ci.child].S;
     const size_t np = (size_t)ci.points;

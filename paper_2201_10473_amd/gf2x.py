@@ -26,6 +26,16 @@ GF2X_MAX_BITS = 131072
 
 KIND_CYCLIC = 0
 KIND_FULL = 1
+KIND_SPARSE = 2
+GF2X_SPARSE_MAX_BITS = 65504
+
+
+def sparse_kind(weight):
+    """Kind of a dense x sparse ring product whose sparse operand has `weight`
+    positions (uint32 values at the item's b offset)."""
+    if not 0 <= int(weight) < (1 << 24):
+        raise ValueError("weight must be below 2^24")
+    return KIND_SPARSE | (int(weight) << 8)
 
 ITEMS_ON_DEVICE = 0x1
 SHARED_A = 0x2

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "gf2x_product.hpp"
+#include "gf2x_sparse_device.hpp"
 #include "gf2x_toeplitz_device.hpp"
 
 thread_local EmuIdx threadIdx;
@@ -34,6 +35,28 @@ unsigned __shfl_xor(unsigned v, int mask, int width) {
     pthread_barrier_wait(&g_bar);
     const unsigned base = t - t % (unsigned)width;
     const unsigned r = g_xch[base + ((t % (unsigned)width) ^ (unsigned)mask)];
+    pthread_barrier_wait(&g_bar);
+    return r;
+}
+
+int emu_ds_bpermute(int addr, int v) {
+    const unsigned t = threadIdx.x;
+    g_xch[t] = (uint32_t)v;
+    pthread_barrier_wait(&g_bar);
+    const unsigned base = t - t % 64u;
+    const int r = (int)g_xch[base + (((unsigned)addr >> 2) & 63u)];
+    pthread_barrier_wait(&g_bar);
+    return r;
+}
+
+int emu_update_dpp(int old, int v, int ctrl) {
+    const unsigned t = threadIdx.x;
+    g_xch[t] = (uint32_t)v;
+    pthread_barrier_wait(&g_bar);
+    const unsigned base = t - t % 64u, l = t % 64u;
+    int r = old;
+    if (ctrl == 0x13C) r = (int)g_xch[base + ((l + 63u) & 63u)];       // wave_ror:1
+    else if (ctrl == 0x134) r = (int)g_xch[base + ((l + 1u) & 63u)];   // wave_rol:1
     pthread_barrier_wait(&g_bar);
     return r;
 }
@@ -257,4 +280,51 @@ extern "C" int emu_staged_words(int which) {
     if (k++ == which) S = gf2x::T::S;
     GF2X_STAGED_LIST(EMU_STAGED_S)
     return S;
+}
+
+// Dense x sparse ring product of one wave (sparse class `which`): a (W(n)
+// words) times the w positions, c = W(n) words.
+namespace {
+struct SparseJob {
+    int which;
+    const uint64_t *a;
+    const uint32_t *pos;
+    uint32_t w, n;
+    uint64_t *c;
+    uint32_t *buf;
+    unsigned tid;
+};
+void *sparse_worker(void *p) {
+    SparseJob *j = static_cast<SparseJob *>(p);
+    threadIdx.x = j->tid;
+    switch (j->which) {
+#define EMU_SPARSE(idx, R) \
+    case idx: gf2x::sparse::product<R>(j->a, j->pos, j->w, j->c, j->n, j->buf); break;
+        GF2X_SPARSE_LIST(EMU_SPARSE)
+        default: break;
+    }
+    return nullptr;
+}
+#define EMU_SPARSE_R(idx, R) R,
+const int kSparseR[] = {GF2X_SPARSE_LIST(EMU_SPARSE_R)};
+}  // namespace
+
+extern "C" int emu_sparse_words_per_lane(int which) { return kSparseR[which]; }
+
+extern "C" int emu_sparse(int which, const uint64_t *a, const uint32_t *pos, uint32_t w, uint64_t *c, uint32_t n) {
+    if (which < 0 || which >= gf2x::sparse::kSparseClasses) return -1;
+    if (64 * kSparseR[which] < 2 * (int)((n + 31) / 32) + 2) return -1;
+    std::vector<uint32_t> buf(64 * (size_t)kSparseR[which]);
+    uint32_t x = 0x9E3779B9u;
+    for (auto &v : buf) v = (x = x * 1664525u + 1013904223u);
+    pthread_barrier_init(&g_bar, nullptr, 64);
+    std::vector<pthread_t> th(64);
+    std::vector<SparseJob> jobs(64);
+    for (int t = 0; t < 64; ++t) {
+        jobs[t] = SparseJob{which, a, pos, w, n, c, buf.data(), (unsigned)t};
+        pthread_create(&th[t], nullptr, sparse_worker, &jobs[t]);
+    }
+    for (int t = 0; t < 64; ++t) pthread_join(th[t], nullptr);
+    pthread_barrier_destroy(&g_bar);
+    return 0;
 }

@@ -26,6 +26,15 @@ extern thread_local EmuIdx threadIdx;
 void __syncthreads();
 unsigned __shfl_up(unsigned v, int delta, int width);
 unsigned __shfl_xor(unsigned v, int mask, int width);
+// Cross-lane moves within a wave of 64 emulated lanes (every lane of the
+// workgroup reaches every call): ds_bpermute returns the value of lane
+// (addr / 4) mod 64; the DPP wave rotations move values one lane up
+// (wave_ror:1, lane l receives lane l - 1) or down (wave_rol:1).
+int emu_ds_bpermute(int addr, int v);
+int emu_update_dpp(int old, int v, int ctrl);
+#define __builtin_amdgcn_ds_bpermute(addr, v) emu_ds_bpermute((addr), (v))
+#define __builtin_amdgcn_update_dpp(old, v, ctrl, rm, bm, bc) emu_update_dpp((old), (v), (ctrl))
+#define __builtin_amdgcn_mov_dpp(v, ctrl, rm, bm, bc) emu_update_dpp(0, (v), (ctrl))
 
 // v_mfma_i32_16x16x64_i8 for one wave of 64 emulated lanes (all lanes of the
 // workgroup reach every call): lane l supplies A[l%16][16*(l/16) + byte],

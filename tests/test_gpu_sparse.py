@@ -1,0 +1,147 @@
+"""Dense x sparse ring products (kind GF2X_SPARSE_KIND(w)): the constant-time
+rotation barrel against the oracle on every item (the sparse operand as the
+dense polynomial of its positions), against the rotation closed form
+(a * s = XOR of rotations of a) on a sample, at the six ring sizes with the
+workload weights, edge sizes and degenerate position sets, mixed with dense
+items in one batch, and recorded in a plan."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2201_10473_amd import gf2x, inputs
+from tests import brute
+from tests.gpu_util import empty_dev, from_dev, to_dev
+from tests.oracle_check import ring_rows
+from tests.sparse_util import dense_of_positions, pack_positions
+
+pytestmark = pytest.mark.gpu
+
+SEED = inputs.SEED_BASE + 40
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = gf2x.Context(0)
+    yield c
+    c.close()
+
+
+def _run_sparse(ctx, n, A, pos_lists, flags=0):
+    """Ring products a_i * s_i (s_i given by positions) in one batched call."""
+    import torch
+    count = A.shape[0]
+    W = oracle.words(n)
+    P, poff = pack_positions(pos_lists)
+    off = np.arange(count, dtype=np.uint64) * W
+    kinds = np.array([gf2x.sparse_kind(len(p)) for p in pos_lists], dtype=np.uint32)
+    items = gf2x.make_items(n, kinds, off, poff, off)
+    dA, dP, dC = to_dev(A.ravel()), to_dev(P), empty_dev(count * W)
+    ctx.mul_batched(items, dC, dA, dP, flags)
+    torch.cuda.synchronize()
+    return from_dev(dC).reshape(count, W)
+
+
+def _check_all(n, A, pos_lists, C):
+    S = np.stack([dense_of_positions(p, n) for p in pos_lists])
+    ref = ring_rows(A, S, n)
+    bad = np.nonzero((ref != C).any(axis=1))[0]
+    assert len(bad) == 0, ("sparse items differ from the oracle", n, bad[:10])
+
+
+@pytest.mark.parametrize("n", inputs.RING_SIZES)
+def test_ring_sizes_workload_weights(ctx, n):
+    count = 300
+    w = inputs.sparse_weight_for(n)
+    A = inputs.dense_batch(n, count, SEED, 0)
+    pos_lists = [inputs.sparse_positions(n, w, SEED, i) for i in range(count)]
+    print("case sparse n=%d w=%d count=%d" % (n, w, count), flush=True)
+    C = _run_sparse(ctx, n, A, pos_lists)
+    _check_all(n, A, pos_lists, C)
+    for i in (0, count - 1):  # the closed form, independent of the oracle's product
+        xa = brute.words_to_int(A[i])
+        expect = 0
+        for q in pos_lists[i]:
+            expect ^= brute.rotate(xa, int(q), n)
+        assert brute.words_to_int(C[i]) == expect, i
+
+
+EDGE = [1, 2, 3, 31, 32, 33, 63, 64, 65, 127, 128, 129, 1000, 4095, 4097, 8160, 8161, 30000, 65503, 65504]
+
+
+@pytest.mark.parametrize("n", EDGE)
+def test_edge_sizes_and_position_sets(ctx, n):
+    """Weights 0, 1, 2, 7 and 150; positions 0 and n-1; repeated positions
+    (they cancel); positions at or above n (taken mod n); junk in a above n."""
+    rng = np.random.default_rng(n)
+    lists = [[], [0], [n - 1], [0, n - 1], [5 % n, 5 % n], [3 % n, 3 % n, 3 % n],
+             list(rng.integers(0, n, 7)), [n, n + 1, 2 * n + 3, 0xFFFFFFFF], list(rng.integers(0, 2 ** 32, 150))]
+    count = len(lists)
+    A = inputs.dense_batch(n, count, SEED + 1, 0)
+    Aj = A.copy()
+    Aj[:, -1] |= ~inputs.top_mask(n)  # bits >= n are ignored
+    print("case sparse edge n=%d" % n, flush=True)
+    C = _run_sparse(ctx, n, Aj, lists)
+    _check_all(n, A, lists, C)
+
+
+def test_rejects_sizes_above_the_sparse_limit(ctx):
+    n = gf2x.GF2X_SPARSE_MAX_BITS + 1
+    W = oracle.words(n)
+    dX = empty_dev(2 * W)
+    items = gf2x.make_items(n, gf2x.sparse_kind(3), 0, 0, 0)
+    with pytest.raises(gf2x.Gf2xError) as e:
+        ctx.mul_batched(items, dX, dX, dX)
+    assert e.value.code == gf2x.GF2X_EINVAL
+
+
+def test_mixed_dense_and_sparse_in_one_batch_and_plan(ctx):
+    """The mixed workload's shape: sizes uniform over the six ring sizes, even
+    items dense x dense, odd items dense x sparse (positions); one batched
+    call, a graph replay and a recorded plan give the oracle's results."""
+    import torch
+    count = 1200
+    rng = np.random.default_rng(5)
+    ns = np.array([inputs.RING_SIZES[i] for i in rng.integers(0, 6, count)], dtype=np.uint32)
+    W = (ns.astype(np.uint64) + 63) // 64
+    off = np.concatenate([[0], np.cumsum(W)[:-1]]).astype(np.uint64)
+    A = np.zeros(int(W.sum()), dtype=np.uint64)
+    Bd = np.zeros(int(W.sum()), dtype=np.uint64)
+    pos_lists = []
+    for i in range(count):
+        n, w0 = int(ns[i]), int(W[i])
+        A[off[i]:off[i] + w0] = inputs.dense(n, SEED + 2, i, 0)
+        if i % 2:
+            pos_lists.append(inputs.sparse_positions(n, inputs.sparse_weight_for(n), SEED + 2, i))
+        else:
+            Bd[off[i]:off[i] + w0] = inputs.dense(n, SEED + 2, i, 1)
+    P, poff = pack_positions(pos_lists)
+    # one b buffer: dense operands first, then the position lists
+    B = np.concatenate([Bd, P])
+    b_off = off.copy()
+    b_off[1::2] = poff + len(Bd)
+    kinds = np.zeros(count, dtype=np.uint32)
+    kinds[1::2] = [gf2x.sparse_kind(len(p)) for p in pos_lists]
+    items = gf2x.make_items(ns, kinds, off, b_off, off)
+    dA, dB = to_dev(A), to_dev(B)
+    # reference operands for the oracle: the dense polynomial of each sparse operand
+    Bref = Bd.copy()
+    for j, i in enumerate(range(1, count, 2)):
+        n = int(ns[i])
+        Bref[off[i]:off[i] + W[i]] = dense_of_positions(pos_lists[j], n)
+    from tests.oracle_check import ring_mismatches
+    for how in ("call", "graph", "plan"):
+        dC = empty_dev(len(A))
+        print("case mixed dense and sparse: %s" % how, flush=True)
+        if how == "call":
+            ctx.mul_batched(items, dC, dA, dB)
+        elif how == "graph":
+            for _ in range(2):
+                ctx.mul_batched(items, dC, dA, dB, gf2x.USE_GRAPH)
+        else:
+            with ctx.plan(items, dC, dA, dB) as plan:
+                plan.launch()
+                plan.launch()
+                torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        C = from_dev(dC)
+        assert ring_mismatches(ns, off, off, off, A, Bref, C) == [], how
