@@ -89,16 +89,17 @@ __device__ __forceinline__ void par_map(u32 *dst, F f) {
 // c (2T words) = a (T words) * b (T words) in F2[X], all in registers.
 //
 // The carry-less product is sum over bits j of a_i of (b << j) placed at word
-// i.  For each bit position j the whole T-word b is shifted left by j once
-// ((T+1) funnel shifts, shared by every a_i), and then for every word a_i the
-// shifted b is XORed into c at word offset i under the mask "bit j of a_i is
-// set": (T+1) v_bitop3 per (i, j).  Each v_bitop3 therefore retires 32
-// bit-pair products, and the low and high halves of the 32x32 products merge
-// into one accumulator word instead of two.
+// i.  The shifted copy sh = b << j is kept as T+1 words and advanced from
+// j - 1 to j by one add-with-carry chain (v_add_co / v_addc: sh + sh with the
+// carry of the word below, full-rate ops), shared by every a_i; then for
+// every word a_i, sh is XORed into c at word offset i under the mask "bit j
+// of a_i is set" (one v_bfe_i32): (T+1) v_bitop3 per (i, j).  Each v_bitop3
+// retires 32 bit-pair products, and the low and high halves of the 32x32
+// products merge into one accumulator word instead of two.
 template <int T>
 struct Unit {
     // VALU lane-ops of one call: j = 0 uses T bfe + T*T bitop3; each of the
-    // other 31 bit positions uses (T+1) shifts + T bfe + T*(T+1) bitop3.
+    // other 31 bit positions uses (T+1) carry-chain adds + T bfe + T*(T+1) bitop3.
     static constexpr long long OPS = (long long)T * T + T + 31LL * (T * T + 3 * T + 1);
 };
 
@@ -106,20 +107,25 @@ template <int T>
 __device__ __forceinline__ void unit_mul(const u32 (&a)[T], const u32 (&b)[T], u32 (&c)[2 * T]) {
 #pragma unroll
     for (int k = 0; k < 2 * T; ++k) c[k] = 0;
+    u32 sh[T + 1];
+#pragma unroll
+    for (int u = 0; u < T; ++u) sh[u] = b[u];
+    sh[T] = 0;
 #pragma unroll
     for (int i = 0; i < T; ++i) {
         const u32 m = bit_mask(a[i], 0);
 #pragma unroll
-        for (int u = 0; u < T; ++u) c[i + u] = xor_and(c[i + u], b[u], m);
+        for (int u = 0; u < T; ++u) c[i + u] = xor_and(c[i + u], sh[u], m);
     }
 #pragma unroll 1
     for (u32 j = 1; j < 32; ++j) {
-        const u32 r = 32u - j;
-        u32 sh[T + 1];
-        sh[0] = b[0] << j;
+        // sh <<= 1 over T+1 words: each word doubled plus the top bit of the word below
+        u32 cy = 0, co;
 #pragma unroll
-        for (int u = 1; u < T; ++u) sh[u] = funnel(b[u], b[u - 1], r);
-        sh[T] = b[T - 1] >> r;
+        for (int u = 0; u <= T; ++u) {
+            sh[u] = __builtin_addc(sh[u], sh[u], cy, &co);
+            cy = co;
+        }
 #pragma unroll
         for (int i = 0; i < T; ++i) {
             const u32 m = bit_mask(a[i], j);
