@@ -176,17 +176,23 @@ def time_mixed(ctx, steps, seed, count=8192):
         if not np.array_equal(C[sl], single_product(ctx, A[sl], B[sl], n)):
             raise AssertionError("mixed workload item %d differs from the single-product path" % i)
     ops = sum(ctx.schedule_info(int(n))[2] for n in ns)
+    # the same batch as one persistent launch (work queue over the direct classes)
+    dF = torch.zeros(len(A), dtype=torch.int64, device="cuda")
+    ms_fused = _plan_ms(ctx, items, dF, dA, dB, steps, gf2x.FUSED)
+    if not torch.equal(dF, dC):
+        raise AssertionError("mixed workload: fused launch differs from the per-class launches")
     return {"products": count, "ms_per_launch": round(ms, 4), "products_per_s": round(count / (ms * 1e-3), 1),
-            "valu_frac": round(ops / (ms * 1e-3) / VALU_PEAK, 4)}
+            "valu_frac": round(ops / (ms * 1e-3) / VALU_PEAK, 4),
+            "fused_ms_per_launch": round(ms_fused, 4), "fused_products_per_s": round(count / (ms_fused * 1e-3), 1)}
 
 
-def _plan_ms(ctx, items, dC, dA, dB, steps):
+def _plan_ms(ctx, items, dC, dA, dB, steps, flags=0):
     """Mean device time of one replay of a recorded batch (HIP events on the
     launch stream), after at least 0.3 s of warm-up replays."""
     import torch
 
     stream = torch.cuda.current_stream()
-    with ctx.plan(items, dC, dA, dB) as plan:
+    with ctx.plan(items, dC, dA, dB, flags) as plan:
         t0 = time.perf_counter()
         while time.perf_counter() - t0 < 0.3:
             plan.launch(stream)

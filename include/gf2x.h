@@ -82,6 +82,7 @@ typedef struct ihipStream_t *gf2x_stream_t;
 #define GF2X_FORCE_PACKED 0x4u     /* use the bit-packed Karatsuba/Toom path even when GF2X_SHARED_A is set */
 #define GF2X_FORCE_TOEPLITZ 0x8u   /* with GF2X_SHARED_A: use the Toeplitz int8-MFMA path                   */
 #define GF2X_USE_GRAPH 0x10u       /* replay a cached HIP graph of the launch (host items only)             */
+#define GF2X_FUSED 0x20u           /* one persistent launch, each item in its one-workgroup class (below)   */
 
 typedef struct gf2x_ctx gf2x_ctx;
 
@@ -125,7 +126,7 @@ int gf2x_mul(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b,
 int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *b,
                     uint32_t n_bits, gf2x_stream_t stream);
 
-/* `count` independent products in one persistent launch.  Item i reads
+/* `count` independent products (persistent kernels).  Item i reads
  * a_base + items[i].a_off and b_base + items[i].b_off and writes
  * c_base + items[i].c_off (sizes per its kind).  Items may mix sizes and
  * kinds.  With host items (default) the library validates n and kind, sorts
@@ -142,6 +143,15 @@ int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_
  * most 64 such graphs and releases the least recently used one first.  Each
  * graph holds its own descriptors and staged workspace within the budget.
  * gf2x_plan_create records a batch without the per-call check.
+ * GF2X_FUSED runs the whole batch as one persistent launch: every workgroup
+ * takes the next item from a device work queue (most expensive first) and
+ * computes it in the size's fastest one-workgroup class.  Only sizes whose
+ * one-workgroup class is one of the classes the schedule table gives the six
+ * ring sizes 12323 ... 57637 are accepted (else GF2X_ENOTSUP), ring and full
+ * kinds; not with GF2X_ITEMS_ON_DEVICE or GF2X_SHARED_A.  Without the flag, a
+ * batch of several size classes runs one launch (or, for a size that spreads
+ * its top Karatsuba/Toom level over workgroups, four) per class, the classes
+ * on up to four internal streams.
  * count == 0 is a no-op.
  * A stream under capture is refused with GF2X_ENOTSUP: the call orders the
  * context's workspace with the context's event and writes descriptors to
@@ -183,7 +193,8 @@ int gf2x_mul_batched_noalloc(gf2x_ctx *ctx, const gf2x_item *items, uint32_t cou
  * device memory counts against the context's budget until the plan is
  * destroyed.  The items array may be freed or reused after the call; the
  * base pointers are baked into the plan and must stay valid while it is used.
- * flags must be 0.  count == 0 gives a plan that launches nothing.
+ * flags: 0 or GF2X_FUSED (as in gf2x_mul_batched).  count == 0 gives a plan
+ * that launches nothing.
  * Errors: GF2X_EINVAL, GF2X_ENOMEM, GF2X_EDEVICE. */
 typedef struct gf2x_plan gf2x_plan;
 int gf2x_plan_create(gf2x_plan **out, gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint64_t *c_base,

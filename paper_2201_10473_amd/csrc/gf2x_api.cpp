@@ -175,7 +175,7 @@ struct Group {
 };
 
 int build_items(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, std::vector<DevItem> &out,
-                std::vector<Group> &groups) {
+                std::vector<Group> &groups, bool fused = false) {
     out.resize(count);
     for (uint32_t i = 0; i < count; ++i) {
         const gf2x_item &it = items[i];
@@ -186,11 +186,20 @@ int build_items(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, std::vect
             if (idx < 0) return GF2X_EINVAL;
             cls = kSparseBase + idx;
         } else if (it.kind == GF2X_KIND_CYCLIC || it.kind == GF2X_KIND_FULL) {
-            cls = ctx->cls_of_w32[(it.n_bits + 31u) / 32u];
+            cls = fused ? ctx->direct_of_w32[(it.n_bits + 31u) / 32u] : ctx->cls_of_w32[(it.n_bits + 31u) / 32u];
         } else {
             return GF2X_EINVAL;
         }
+        if (fused && (is_sparse_class(cls) || !fused_class(cls))) return GF2X_ENOTSUP;
         out[i] = DevItem{it.n_bits, it.kind, (uint32_t)cls, 0u, it.a_off, it.b_off, it.c_off};
+    }
+    if (fused) {
+        // one launch; the work queue hands out the most expensive items first
+        std::stable_sort(out.begin(), out.end(), [](const DevItem &x, const DevItem &y) {
+            return class_info((int)x.cls).ops > class_info((int)y.cls).ops;
+        });
+        groups.assign(1, Group{kFusedCls, 0, count});
+        return GF2X_OK;
     }
     std::stable_sort(out.begin(), out.end(), [](const DevItem &x, const DevItem &y) {
         const int sx = class_info((int)x.cls).S, sy = class_info((int)y.cls).S;
@@ -251,9 +260,11 @@ void fit_staged(gf2x_ctx *ctx, std::vector<Group> &groups, size_t have) {
 }
 
 int launch_one(gf2x_ctx *ctx, const Group &g, const DevItem *d_items, char *&ws, uint64_t *c, const uint64_t *a,
-               const uint64_t *b, hipStream_t s) {
+               const uint64_t *b, hipStream_t s, uint32_t *queue = nullptr) {
     hipError_t e;
-    if (class_info(g.cls).child >= 0) {
+    if (g.cls == kFusedCls) {
+        e = launch_fused(d_items + g.first, g.count, c, a, b, queue, ctx->num_cu, s);
+    } else if (class_info(g.cls).child >= 0) {
         e = launch_staged(g.cls, d_items + g.first, g.count, c, a, b, ws, ctx->num_cu, s);
         ws += (staged_workspace_bytes(g.cls, g.count) + 255) / 256 * 256;
     } else {
@@ -267,9 +278,9 @@ int launch_one(gf2x_ctx *ctx, const Group &g, const DevItem *d_items, char *&ws,
 // joined back to it with events, so that different sizes overlap.  Staged
 // groups carve their regions out of ws in group order.
 int launch_groups(gf2x_ctx *ctx, const DevItem *d_items, const std::vector<Group> &groups, uint64_t *c,
-                  const uint64_t *a, const uint64_t *b, void *ws, hipStream_t s) {
+                  const uint64_t *a, const uint64_t *b, void *ws, hipStream_t s, uint32_t *queue = nullptr) {
     char *wp = reinterpret_cast<char *>(ws);
-    if (groups.size() == 1) return launch_one(ctx, groups[0], d_items, wp, c, a, b, s);
+    if (groups.size() == 1) return launch_one(ctx, groups[0], d_items, wp, c, a, b, s, queue);
     int rc = ensure_forks(ctx);
     if (rc) return rc;
     const int K = std::min<int>(gf2x_ctx::kForks, (int)groups.size());
@@ -310,7 +321,7 @@ int record_graph(gf2x_ctx *ctx, const std::vector<DevItem> &host, std::vector<Gr
     g = GraphEntry{};
     fit_staged(ctx, groups, 0);
     const size_t sb = staged_bytes(groups);
-    const size_t ib = (host.size() * sizeof(DevItem) + 255) / 256 * 256;
+    const size_t ib = (host.size() * sizeof(DevItem) + 255) / 256 * 256 + 256;  // + fused queue counters
     if (ctx->allocated + sb + ib > ctx->budget) return GF2X_ENOMEM;
     if (hipMalloc(&g.items, ib) != hipSuccess) {
         g.items = nullptr;
@@ -324,16 +335,19 @@ int record_graph(gf2x_ctx *ctx, const std::vector<DevItem> &host, std::vector<Gr
     }
     g.bytes = ib + sb;
     ctx->allocated += g.bytes;
-    hipError_t e = use_copy_stream
+    g.queue = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(g.items) + ib - 256);
+    hipError_t e = use_copy_stream ? hipMemsetAsync(g.queue, 0, 256, copy_stream) : hipMemset(g.queue, 0, 256);
+    if (e == hipSuccess)
+        e = use_copy_stream
                        ? hipMemcpyAsync(g.items, host.data(), host.size() * sizeof(DevItem), hipMemcpyHostToDevice,
                                         copy_stream)
-                       : hipMemcpy(g.items, host.data(), host.size() * sizeof(DevItem), hipMemcpyHostToDevice);
+                : hipMemcpy(g.items, host.data(), host.size() * sizeof(DevItem), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&g.done, hipEventDisableTiming);
     hipStream_t cap = nullptr;
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        int lrc = launch_groups(ctx, g.items, groups, c_base, a_base, b_base, g.staged_ws, cap);
+        int lrc = launch_groups(ctx, g.items, groups, c_base, a_base, b_base, g.staged_ws, cap, g.queue);
         hipError_t e2 = hipStreamEndCapture(cap, &g.graph);
         e = lrc ? hipErrorLaunchFailure : e2;
     }
@@ -482,7 +496,13 @@ int gf2x_create(gf2x_ctx **out, const gf2x_opts *opts) {
     default_table(ctx);
     if (o.tune_cache) load_tune_cache(ctx, o.tune_cache);
     direct_table(ctx);
-    const int rc = upload_direct_table(ctx);
+    int rc = upload_direct_table(ctx);
+    if (rc == GF2X_OK) {
+        e = hipMalloc(&ctx->d_queue, 256);
+        if (e == hipSuccess) e = hipMemset(ctx->d_queue, 0, 256);
+        if (e == hipSuccess) ctx->allocated += 256;
+        else rc = device_error(e);
+    }
     if (rc) {
         gf2x_destroy(ctx);
         return rc;
@@ -505,6 +525,7 @@ void gf2x_destroy(gf2x_ctx *ctx) {
     if (ctx->d_items) hipFree(ctx->d_items);
     for (gf2x::DevItem *chunk : ctx->single_chunks) hipFree(chunk);
     if (ctx->d_cls) hipFree(ctx->d_cls);
+    if (ctx->d_queue) hipFree(ctx->d_queue);
     if (ctx->ws_free) hipEventDestroy(ctx->ws_free);
     delete ctx;
 }
@@ -542,8 +563,10 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
     if (!items || !c_base || !a_base || !b_base) return GF2X_EINVAL;
     if (!aligned8(c_base) || !aligned8(a_base) || !aligned8(b_base)) return GF2X_EINVAL;
     const uint32_t known = GF2X_ITEMS_ON_DEVICE | GF2X_SHARED_A | GF2X_FORCE_PACKED | GF2X_FORCE_TOEPLITZ |
-                           GF2X_USE_GRAPH;
+                           GF2X_USE_GRAPH | GF2X_FUSED;
     if (flags & ~known) return GF2X_EINVAL;
+    const bool fused = (flags & GF2X_FUSED) != 0;
+    if (fused && (flags & (GF2X_ITEMS_ON_DEVICE | GF2X_SHARED_A))) return GF2X_ENOTSUP;
     if ((flags & GF2X_FORCE_PACKED) && (flags & GF2X_FORCE_TOEPLITZ)) return GF2X_EINVAL;
     if ((flags & GF2X_FORCE_TOEPLITZ) && !(flags & GF2X_SHARED_A)) return GF2X_ENOTSUP;
     const bool dev_items = (flags & GF2X_ITEMS_ON_DEVICE) != 0;
@@ -596,7 +619,7 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
         }
         std::vector<DevItem> host;
         std::vector<Group> groups;
-        int rc = build_items(ctx, items, count, host, groups);
+        int rc = build_items(ctx, items, count, host, groups, fused);
         if (rc) return rc;
         while (ctx->graphs.size() >= gf2x_ctx::kMaxGraphs) {
             auto lru = ctx->graphs.begin();
@@ -611,7 +634,7 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
             // release the cached entries (their budget) and try once more
             for (auto &kv : ctx->graphs) release_entry(ctx, kv.second);
             ctx->graphs.clear();
-            rc = build_items(ctx, items, count, host, groups);
+            rc = build_items(ctx, items, count, host, groups, fused);
             if (rc == GF2X_OK) rc = record_graph(ctx, host, groups, c_base, a_base, b_base, g, s, true);
         }
         if (rc) return rc;
@@ -623,7 +646,7 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
 
     std::vector<DevItem> host;
     std::vector<Group> groups;
-    int rc = build_items(ctx, items, count, host, groups);
+    int rc = build_items(ctx, items, count, host, groups, fused);
     if (rc) return rc;
     rc = ensure_items(ctx, count);
     if (rc) return rc;
@@ -632,7 +655,7 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
     if (rc) return rc;
     if (ctx->ws_used) HIP_TRY(hipStreamWaitEvent(s, ctx->ws_free, 0));
     HIP_TRY(hipMemcpyAsync(ctx->d_items, host.data(), count * sizeof(DevItem), hipMemcpyHostToDevice, s));
-    rc = launch_groups(ctx, ctx->d_items, groups, c_base, a_base, b_base, ctx->staged_ws, s);
+    rc = launch_groups(ctx, ctx->d_items, groups, c_base, a_base, b_base, ctx->staged_ws, s, ctx->d_queue);
     if (rc) return rc;
     HIP_TRY(hipEventRecord(ctx->ws_free, s));
     ctx->ws_used = true;
@@ -681,7 +704,7 @@ int gf2x_plan_create(gf2x_plan **out, gf2x_ctx *ctx, const gf2x_item *items, uin
                      const uint64_t *a_base, const uint64_t *b_base, uint32_t flags) {
     if (!out) return GF2X_EINVAL;
     *out = nullptr;
-    if (!ctx || flags != 0) return GF2X_EINVAL;
+    if (!ctx || (flags & ~GF2X_FUSED)) return GF2X_EINVAL;
     if (count && (!items || !c_base || !a_base || !b_base)) return GF2X_EINVAL;
     if (!aligned8(c_base) || !aligned8(a_base) || !aligned8(b_base)) return GF2X_EINVAL;
     HIP_TRY(hipSetDevice(ctx->device));
@@ -691,7 +714,7 @@ int gf2x_plan_create(gf2x_plan **out, gf2x_ctx *ctx, const gf2x_item *items, uin
     if (count) {
         std::vector<DevItem> host;
         std::vector<Group> groups;
-        int rc = build_items(ctx, items, count, host, groups);
+        int rc = build_items(ctx, items, count, host, groups, (flags & GF2X_FUSED) != 0);
         if (rc == GF2X_OK) rc = record_graph(ctx, host, groups, c_base, a_base, b_base, plan->g, nullptr, false);
         if (rc) {
             delete plan;

@@ -21,6 +21,7 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     DevItem *items = nullptr;  // private copy of the descriptors
+    uint32_t *queue = nullptr; // work-queue counters of a fused launch (inside the items allocation)
     void *staged_ws = nullptr; // private workspace of the staged groups
     size_t bytes = 0;          // device bytes of items + staged_ws (counted in the budget)
     hipEvent_t done = nullptr;
@@ -50,6 +51,7 @@ struct gf2x_ctx {
                                                // staged)
     uint8_t *d_cls = nullptr;                  // device copy of direct_of_w32
     gf2x::DevItem *d_items = nullptr;    // workspace for host item descriptors
+    uint32_t *d_queue = nullptr;         // work-queue counters of fused launches (same guard)
     size_t d_items_cap = 0;
     hipEvent_t ws_free = nullptr;  // recorded after the last launch reading d_items / staged_ws
     void *staged_ws = nullptr;     // workspace of staged classes (point operands and products)

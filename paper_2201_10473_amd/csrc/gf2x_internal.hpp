@@ -18,7 +18,9 @@ constexpr uint32_t kKindSparse = 2;  // low byte of the kind; the weight is kind
 static_assert(kKindSparse == GF2X_KIND_SPARSE, "kind code as declared in gf2x.h");
 // Size classes of dense x sparse products get the ids kSparseBase + index.
 constexpr int kSparseBase = 64;
-inline bool is_sparse_class(int cls) { return cls >= kSparseBase; }
+inline bool is_sparse_class(int cls) { return cls >= kSparseBase && cls < kSparseBase + 8; }
+// The group id of a fused launch (every item in its direct class, one kernel).
+constexpr int kFusedCls = 1000;
 constexpr uint32_t kMaxBits = 131072;
 constexpr uint32_t kMaxWords32 = kMaxBits / 32;
 
@@ -64,6 +66,14 @@ const ClassInfo &class_info(int cls);
 int sparse_class_for(uint32_t n);
 int sparse_words_per_lane(int idx);
 hipError_t prepare_sparse_kernels();
+
+// One persistent launch over items of the fused class set (gf2x_kern_fused.hip):
+// whether a direct class belongs to it, and the launcher; queue: two uint32
+// counters, zero before the first launch (the kernel leaves them zero).
+bool fused_class(int cls);
+hipError_t prepare_fused_kernel();
+hipError_t launch_fused(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
+                        const uint64_t *b_base, uint32_t *queue, int num_cu, hipStream_t s);
 hipError_t launch_sparse(int idx, const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
                          const uint64_t *b_base, int num_cu, hipStream_t s);
 hipError_t prepare_kernels();

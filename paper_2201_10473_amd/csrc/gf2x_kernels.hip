@@ -114,7 +114,10 @@ static bool init_sparse_info() {
 }
 static const bool kSparseInfoReady = init_sparse_info();
 
+static const ClassInfo kFusedInfo{kFusedCls, "FUSED", 0, 0, 0, 0, -1, kFusedCls, 0};
+
 const ClassInfo &class_info(int cls) {
+    if (cls == kFusedCls) return kFusedInfo;
     return is_sparse_class(cls) ? kSparseInfo[cls - kSparseBase] : kClassInfo[cls];
 }
 
@@ -147,6 +150,8 @@ hipError_t prepare_kernels() {
     hipError_t e = prepare_staged_kernels();
     if (e != hipSuccess) return e;
     e = prepare_sparse_kernels();
+    if (e != hipSuccess) return e;
+    e = prepare_fused_kernel();
     if (e != hipSuccess) return e;
     for (int c = 0; c < kNumDirect; ++c) {
         e = set_lds_limit(kSingle[c], kClassInfo[c].lds_bytes);

@@ -42,6 +42,7 @@ SHARED_A = 0x2
 FORCE_PACKED = 0x4
 FORCE_TOEPLITZ = 0x8
 USE_GRAPH = 0x10
+FUSED = 0x20
 
 # Layout of struct gf2x_item.
 ITEM_DTYPE = np.dtype(
@@ -271,9 +272,9 @@ class Context:
             "gf2x_mul_batched_noalloc",
         )
 
-    def plan(self, items, c_base, a_base, b_base):
+    def plan(self, items, c_base, a_base, b_base, flags=0):
         """Record a batch (host items) once for replays with constant host work."""
-        return Plan(self, items, c_base, a_base, b_base)
+        return Plan(self, items, c_base, a_base, b_base, flags)
 
     def inv_cyclic_batched(self, items, c_base, a_base, stream=None):
         """Inverses in F2[X]/(X^n - 1) (n an odd prime; all items of one n) of
@@ -314,14 +315,14 @@ class Context:
 class Plan:
     """A recorded batch (gf2x_plan_* in the C ABI); launch() replays it."""
 
-    def __init__(self, ctx, items, c_base, a_base, b_base):
+    def __init__(self, ctx, items, c_base, a_base, b_base, flags=0):
         self._lib = load()
         self._ctx = ctx
         items = np.ascontiguousarray(items, dtype=ITEM_DTYPE)
         h = ctypes.c_void_p()
         _check(
             self._lib.gf2x_plan_create(ctypes.byref(h), ctx._h, items.ctypes.data, len(items), _ptr(c_base),
-                                       _ptr(a_base), _ptr(b_base), 0),
+                                       _ptr(a_base), _ptr(b_base), int(flags)),
             "gf2x_plan_create",
         )
         self._h = h
