@@ -543,7 +543,7 @@ def main():
     ap.add_argument("--only-n", type=int, default=0, help="time only this ring size (profiling runs)")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=0,
-                    help="requests per serving rate (default: 0.5 s of traffic, 20000 to 100000)")
+                    help="requests per serving rate (default 100000)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -659,14 +659,22 @@ def main():
 
             # the server gets a context of its own, as a serving process would
             with gf2x.Context(0) as sctx:
-                for rate in (10000, 100000, 500000):
-                    log("serving: Poisson %d req/s" % rate)
-                    count = args.serving_requests or min(100000, max(20000, int(rate * 0.5)))
-                    res, bufs = serve.run(sctx, rate, count, inputs.SEED_BASE + 5)
+                runs = [(rate, 0) for rate in (10000, 30000, 100000, 300000, 500000)] + [(100000, 8 << 20)]
+                for rate, budget in runs:
+                    log("serving: Poisson %d req/s%s" % (rate, ", 8 MiB budget" if budget else ""))
+                    count = args.serving_requests or 100000
+                    res, bufs = serve.run(sctx, rate, count, inputs.SEED_BASE + 5, hbm_budget_bytes=budget)
                     serve.check_against_batched(sctx, *bufs)
+                    res["hbm_budget_bytes"] = budget or 256 << 20
                     serving.append(res)
-                    log("  achieved %.0f req/s p50 %.1f us p99 %.1f us" % (res["achieved_rate"], res["p50_us"],
-                                                                           res["p99_us"]))
+                    st = res["server"]
+                    log("  achieved %.0f req/s p50 %.1f us p99 %.1f us; batches %d (%d phased), host per batch "
+                        "pack %.1f issue %.1f retire %.1f us; max batch %.0f us, device %.0f us, loop %.0f us"
+                        % (res["achieved_rate"], res["p50_us"], res["p99_us"], st["batches"], st["phased_batches"],
+                           st["host_pack_ns"] / 1e3 / max(1, st["batches"]),
+                           st["host_issue_ns"] / 1e3 / max(1, st["batches"]),
+                           st["host_retire_ns"] / 1e3 / max(1, st["batches"]), st["batch_max_ns"] / 1e3,
+                           st["device_max_ns"] / 1e3, st["loop_busy_max_ns"] / 1e3))
                 from paper_2201_10473_amd import hqc_trace
 
                 log("HQC-shaped trace: 5000 operations (chains of 1-3 dependent products), 20000 op/s")

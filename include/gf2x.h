@@ -265,8 +265,10 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
  * on the device.  A batch of at most 256 requests runs each product in its
  * size's lowest-latency class (possibly staged, using a per-slot workspace
  * within half of the budget; with many streams or a small budget the limit
- * is halved until the workspaces fit, down to none); larger batches run one
- * workgroup per product.  Results are identical to gf2x_mul_cyclic of the
+ * is halved until the workspaces fit, down to none), as three phase kernels
+ * for all of its sizes (evaluations, one-workgroup products, interpolations)
+ * when every class it needs is one the phase kernels hold; larger batches run
+ * one workgroup per product, one launch per size class.  Results are identical to gf2x_mul_cyclic of the
  * same operands (every class computes the same exact product). */
 typedef struct gf2x_srv gf2x_srv;
 
@@ -283,7 +285,20 @@ typedef struct gf2x_srv_stats {
     uint64_t submitted, admitted, completed, refused, pending;
     uint64_t batches, launches;
     uint32_t max_batch, max_batch_seen, max_slots_busy;
-    uint64_t hbm_bytes; /* device memory held by the slots */
+    uint64_t hbm_bytes;        /* device memory held by the slots                                     */
+    uint64_t phased_batches;   /* batches run as three phase kernels                                  */
+    /* Host time of the scheduler per batch, in ns (totals and maxima): packing
+     * the operands and descriptors into the pinned buffer, issuing the copies
+     * and launches, handing the results back.  device_max_ns is the longest
+     * time from a batch's last HIP call to its completion being seen (device
+     * work plus polling), batch_max_ns the longest from admission to the
+     * results handed back, loop_busy_max_ns the longest scheduler iteration
+     * without its idle wait, wake_late_max_ns the longest overshoot of an
+     * idle wait.  Together they place a slow batch in host or device time. */
+    uint64_t host_pack_ns, host_issue_ns, host_retire_ns;
+    uint64_t host_pack_max_ns, host_issue_max_ns, host_retire_max_ns;
+    uint64_t device_max_ns, batch_max_ns, loop_busy_max_ns, wake_late_max_ns;
+    uint64_t loop_busy_max_at_ns; /* steady-clock start of the longest scheduler iteration */
 } gf2x_srv_stats;
 
 /* Start a server on ctx (which must outlive it).  Errors: GF2X_EINVAL,
@@ -304,8 +319,12 @@ int gf2x_srv_submit(gf2x_srv *srv, uint32_t count, const uint32_t *n_bits, const
                     const uint64_t *c_off, const uint64_t *arrival_ns, uint64_t *first_ticket);
 
 /* Completion stamps (steady clock ns; 0 = not yet complete) of tickets
- * first_ticket .. first_ticket+count-1.  Errors: GF2X_EINVAL, or the device
- * error the scheduler hit. */
+ * first_ticket .. first_ticket+count-1.  The server keeps a stamp until it has
+ * been returned here and every earlier ticket's stamp has been returned too;
+ * after that, reading the ticket again gives 1 (completed, stamp no longer
+ * kept).  So the memory held for stamps is bounded by the tickets not yet
+ * read.  Errors: GF2X_EINVAL (a ticket not yet issued), or the device error
+ * the scheduler hit. */
 int gf2x_srv_completion(gf2x_srv *srv, uint64_t first_ticket, uint32_t count, uint64_t *done_ns);
 
 /* Wait until every submitted request has completed (timeout_ms 0 = 1 hour).

@@ -71,6 +71,24 @@ hipError_t prepare_sparse_kernels();
 // whether a direct class belongs to it, and the launcher; queue: two uint32
 // counters, zero before the first launch (the kernel leaves them zero).
 bool fused_class(int cls);
+
+// A batch of mixed sizes in three launches (gf2x_kern_phase.hip): the
+// evaluations of its staged items, all one-workgroup products (the staged
+// items' point products, flagged by pad = 1 and addressed in the workspace,
+// and the direct items), the interpolations.  ws_off holds two 32-bit-word
+// offsets per staged item (its point operands, its point products).
+bool phase_product_class(int cls);
+int phase_eval_lds(int cls);
+int phase_interp_lds(int cls);
+hipError_t prepare_phase_kernels();
+hipError_t launch_phase_eval(const DevItem *items, const uint64_t *ws_off, uint32_t count, int lds,
+                             const uint64_t *a_base, const uint64_t *b_base, uint32_t *ws, int num_cu,
+                             hipStream_t s);
+hipError_t launch_phase_products(const DevItem *items, uint32_t count, int lds, uint64_t *c_base,
+                                 const uint64_t *a_base, const uint64_t *b_base, uint64_t *ws, int num_cu,
+                                 hipStream_t s);
+hipError_t launch_phase_interp(const DevItem *items, const uint64_t *ws_off, uint32_t count, int lds,
+                               uint64_t *c_base, const uint32_t *ws, int num_cu, hipStream_t s);
 hipError_t prepare_fused_kernel();
 hipError_t launch_fused(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
                         const uint64_t *b_base, uint32_t *queue, int num_cu, hipStream_t s);

@@ -153,6 +153,8 @@ hipError_t prepare_kernels() {
     if (e != hipSuccess) return e;
     e = prepare_fused_kernel();
     if (e != hipSuccess) return e;
+    e = prepare_phase_kernels();
+    if (e != hipSuccess) return e;
     for (int c = 0; c < kNumDirect; ++c) {
         e = set_lds_limit(kSingle[c], kClassInfo[c].lds_bytes);
         if (e != hipSuccess) return e;

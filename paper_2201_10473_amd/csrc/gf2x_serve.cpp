@@ -13,8 +13,12 @@
 //      results back (pinned -> caller's buffer) and stamps the completion time;
 //   2. launch: if a slot is free and requests whose arrival time has passed
 //      are waiting, pack up to max_batch of them (descriptors, a, b) into the
-//      slot's pinned buffer, copy to the device, launch one batched kernel per
-//      size class present, copy the results back, record the event.
+//      slot's pinned buffer, copy to the device, launch the products, copy the
+//      results back, record the event.  A batch of at most a few hundred
+//      requests runs as three phase kernels whatever sizes it holds (the
+//      evaluations of the sizes whose products are spread over workgroups, all
+//      one-workgroup products, the interpolations); a larger batch runs one
+//      persistent launch per size class, the classes on sub-streams.
 // While one slot's batch runs, the next arrivals form the next batch on
 // another slot: new requests join while earlier ones are on the GPU, and
 // batches on different streams overlap on the device.
@@ -71,6 +75,8 @@ constexpr uint32_t kSmallBatch = 256;
 constexpr uint64_t kBusyPollNs = 5000;
 
 struct Slot {
+    uint64_t t_admit = 0, t_issued = 0;  // batch admitted, last HIP call of the batch returned
+    bool phased = false;
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     hipStream_t sub[kSubStreams] = {};   // class groups of one batch run side by side
@@ -78,6 +84,7 @@ struct Slot {
     char *host = nullptr;   // pinned: [items | a | b | c]
     char *dev = nullptr;    // device: same layout
     char *ws = nullptr;     // device workspace of the staged groups of a small batch
+    char *ph_host = nullptr, *ph_dev = nullptr;  // descriptors of a phased batch (pinned, device)
     std::vector<Request> reqs;
     std::vector<uint64_t> c_off;  // word offset of each request's result in the c region
     size_t c_region = 0;          // byte offset of the c region
@@ -92,12 +99,18 @@ struct gf2x_srv {
     uint32_t max_bits = 0, max_batch = 0, max_pending = 0;
     size_t slot_bytes = 0;
     size_t ws_bytes = 0;  // per slot; 0 when the budget leaves no room
+    size_t ph_bytes = 0;  // per slot: descriptors of a phased batch
     uint32_t small_limit = 0;  // batches up to this size use the staged classes
     std::vector<Slot> slots;
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Request> pending;
-    std::vector<uint64_t> done_ns;  // per ticket; 0 = not done
+    // completion stamps of tickets base_ticket, base_ticket + 1, ...; 0 = not
+    // done; bit 63 set once the stamp has been returned by gf2x_srv_completion.
+    // Returned stamps at the front are dropped, so the window holds only the
+    // tickets the caller has not read yet (plus those behind one it has not).
+    std::deque<uint64_t> done_ns;
+    uint64_t base_ticket = 0;
     std::atomic<uint64_t> completed{0};
     uint64_t next_ticket = 0;
     std::atomic<bool> stop{false};
@@ -148,10 +161,16 @@ size_t retire(gf2x_srv *srv) {
             const uint64_t W = (r.n + 63u) / 64u;
             std::memcpy(r.c, sl.host + sl.c_region + sl.c_off[i] * 8, W * 8);
         });
+        const uint64_t t_out = now_ns();
         {
             std::lock_guard<std::mutex> lk(srv->mu);
-            for (const Request &r : sl.reqs) srv->done_ns[r.ticket] = t;
+            for (const Request &r : sl.reqs) srv->done_ns[r.ticket - srv->base_ticket] = t;
             srv->completed += sl.reqs.size();
+            gf2x_srv_stats &st = srv->stats;
+            st.host_retire_ns += t_out - t;
+            st.host_retire_max_ns = std::max(st.host_retire_max_ns, t_out - t);
+            st.device_max_ns = std::max(st.device_max_ns, t - sl.t_issued);
+            st.batch_max_ns = std::max(st.batch_max_ns, t_out - sl.t_admit);
         }
         done += sl.reqs.size();
         sl.reqs.clear();
@@ -181,98 +200,183 @@ bool launch(gf2x_srv *srv) {
     }
     if (sl->reqs.empty()) return false;
     const uint32_t count = (uint32_t)sl->reqs.size();
-    // layout: [DevItem x max_batch | a words | b words | c words]; operand and
-    // result regions sized for max_batch requests of the largest n
+    // layout: [DevItem x max_batch | a words | b words (right after the batch's
+    // a words) | c words]; the regions are sized for max_batch requests of
+    // the largest n
     const uint64_t Wmax = (srv->max_bits + 63u) / 64u;
     const size_t items_bytes = round_up((size_t)srv->max_batch * sizeof(DevItem), 256);
     const size_t region = (size_t)srv->max_batch * Wmax * 8;
-    const size_t a_at = items_bytes, b_at = a_at + region, c_at = b_at + region;
-    DevItem *items = reinterpret_cast<DevItem *>(sl->host);
-    std::vector<DevItem> tmp(count);
+    const size_t a_at = items_bytes, c_at = a_at + 2 * region;
     sl->c_off.resize(count);
     uint64_t off = 0;
     const bool small = count <= srv->small_limit && srv->ws_bytes > 0;
+    std::vector<int> cls_of(count);
+    bool phased = small;
     for (uint32_t i = 0; i < count; ++i) {
         const Request &r = sl->reqs[i];
-        const uint64_t W = (r.n + 63u) / 64u;
         const uint32_t w32 = (r.n + 31u) / 32u;
         const int cls = small ? srv->ctx->single_of_w32[w32] : srv->ctx->direct_of_w32[w32];
-        tmp[i] = DevItem{r.n, kKindCyclic, (uint32_t)cls, 0u, off, off, off};
+        cls_of[i] = cls;
+        const ClassInfo &ci = class_info(cls);
+        if (!phase_product_class(ci.child >= 0 ? ci.child : cls)) phased = false;
         sl->c_off[i] = off;
-        off += W;
+        off += (r.n + 63u) / 64u;
     }
+    const size_t b_at = a_at + off * 8;
     parallel_for(count, [&](uint32_t i) {
         const Request &r = sl->reqs[i];
         const uint64_t W = (r.n + 63u) / 64u;
         std::memcpy(sl->host + a_at + sl->c_off[i] * 8, r.a, W * 8);
         std::memcpy(sl->host + b_at + sl->c_off[i] * 8, r.b, W * 8);
     });
-    // group by class (largest first) so that each class is one launch
-    std::stable_sort(tmp.begin(), tmp.end(), [](const DevItem &x, const DevItem &y) {
-        return class_info((int)x.cls).S > class_info((int)y.cls).S ||
-               (class_info((int)x.cls).S == class_info((int)y.cls).S && x.cls < y.cls);
-    });
-    std::memcpy(items, tmp.data(), count * sizeof(DevItem));
     sl->c_region = c_at;
     sl->c_bytes = off * 8;
-    hipError_t e = hipMemcpyAsync(sl->dev, sl->host, count * sizeof(DevItem), hipMemcpyHostToDevice, sl->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(sl->dev + a_at, sl->host + a_at, off * 8, hipMemcpyHostToDevice, sl->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(sl->dev + b_at, sl->host + b_at, off * 8, hipMemcpyHostToDevice, sl->stream);
-    const DevItem *d_items = reinterpret_cast<const DevItem *>(sl->dev);
     uint64_t *dc = reinterpret_cast<uint64_t *>(sl->dev + c_at);
     const uint64_t *da = reinterpret_cast<const uint64_t *>(sl->dev + a_at);
     const uint64_t *db = reinterpret_cast<const uint64_t *>(sl->dev + b_at);
-    // one launch per class group; with several groups they go to the slot's
-    // sub-streams (forked after the copies, joined before the copy back), a
-    // single group runs on the slot's stream
-    int groups = 0;
-    for (uint32_t i = 0; i < count; ++i) groups += (i == 0 || tmp[i].cls != tmp[i - 1].cls);
-    const bool fork = groups > 1;
-    if (e == hipSuccess && fork) e = hipEventRecord(sl->fork, sl->stream);
-    uint32_t first = 0;
-    int g = 0;
-    char *wp = sl->ws;  // staged groups carve their workspace regions in order
-    while (e == hipSuccess && first < count) {
-        uint32_t last = first;
-        while (last < count && tmp[last].cls == tmp[first].cls) ++last;
-        hipStream_t sub = fork ? sl->sub[g % kSubStreams] : sl->stream;
-        if (fork && g < kSubStreams) e = hipStreamWaitEvent(sub, sl->fork, 0);
-        const int cls = (int)tmp[first].cls;
-        if (e == hipSuccess && class_info(cls).child >= 0) {
-            e = launch_staged(cls, d_items + first, last - first, dc, da, db, wp, srv->ctx->num_cu, sub);
-            wp += round_up(staged_workspace_bytes(cls, last - first), 256);
-        } else if (e == hipSuccess) {
-            e = launch_batched(cls, d_items + first, last - first, dc, da, db, srv->ctx->num_cu, sub);
+    hipError_t e = hipSuccess;
+    uint64_t t_packed = now_ns();
+    uint32_t launches = 0;
+    if (phased) {
+        // three phase kernels: descriptors of the staged items (with their two
+        // workspace offsets, in 32-bit words) and of every one-workgroup product
+        std::vector<DevItem> st, pr;
+        std::vector<uint64_t> wso;
+        st.reserve(count);
+        wso.reserve(2 * count);
+        pr.reserve(8 * (size_t)count);
+        uint64_t wsw = 0;
+        int eval_lds = 0, prod_lds = 0, interp_lds = 0;
+        for (uint32_t i = 0; i < count; ++i) {
+            const Request &r = sl->reqs[i];
+            const int cls = cls_of[i];
+            const ClassInfo &ci = class_info(cls);
+            const DevItem it{r.n, kKindCyclic, (uint32_t)cls, 0u, sl->c_off[i], sl->c_off[i], sl->c_off[i]};
+            if (ci.child >= 0) {
+                const uint64_t S1 = (uint64_t)class_info(ci.child).S, per = 2 * (uint64_t)ci.points * S1;
+                const uint64_t in = wsw, out = wsw + per;
+                wsw += 2 * per;
+                st.push_back(it);
+                wso.push_back(in);
+                wso.push_back(out);
+                for (int e2 = 0; e2 < ci.points; ++e2)
+                    pr.push_back(DevItem{(uint32_t)(32 * S1), kKindFull, (uint32_t)ci.child, 1u, in / 2 + e2 * S1,
+                                         in / 2 + e2 * S1 + S1 / 2, out / 2 + e2 * S1});
+                eval_lds = std::max(eval_lds, phase_eval_lds(cls));
+                interp_lds = std::max(interp_lds, phase_interp_lds(cls));
+                prod_lds = std::max(prod_lds, class_info(ci.child).lds_bytes);
+            } else {
+                pr.push_back(it);
+                prod_lds = std::max(prod_lds, ci.lds_bytes);
+            }
         }
-        {
-            std::lock_guard<std::mutex> lk(srv->mu);
-            srv->stats.launches++;
+        // the most expensive products first
+        std::stable_sort(pr.begin(), pr.end(), [](const DevItem &x, const DevItem &y) {
+            return class_info((int)x.cls).ops > class_info((int)y.cls).ops;
+        });
+        const size_t st_at = 0, wso_at = round_up(st.size() * sizeof(DevItem), 256);
+        const size_t pr_at = wso_at + round_up(wso.size() * 8, 256);
+        const size_t ph_used = pr_at + pr.size() * sizeof(DevItem);
+        if (ph_used > srv->ph_bytes || wsw * 4 > srv->ws_bytes) {
+            e = hipErrorInvalidValue;  // cannot happen: both are sized for small_limit requests
+        } else {
+            std::memcpy(sl->ph_host + st_at, st.data(), st.size() * sizeof(DevItem));
+            std::memcpy(sl->ph_host + wso_at, wso.data(), wso.size() * 8);
+            std::memcpy(sl->ph_host + pr_at, pr.data(), pr.size() * sizeof(DevItem));
+            t_packed = now_ns();
+            const DevItem *d_st = reinterpret_cast<const DevItem *>(sl->ph_dev + st_at);
+            const uint64_t *d_wso = reinterpret_cast<const uint64_t *>(sl->ph_dev + wso_at);
+            const DevItem *d_pr = reinterpret_cast<const DevItem *>(sl->ph_dev + pr_at);
+            const int ncu = srv->ctx->num_cu;
+            e = hipMemcpyAsync(sl->ph_dev, sl->ph_host, ph_used, hipMemcpyHostToDevice, sl->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(sl->dev + a_at, sl->host + a_at, 2 * off * 8, hipMemcpyHostToDevice, sl->stream);
+            if (e == hipSuccess)
+                e = launch_phase_eval(d_st, d_wso, (uint32_t)st.size(), eval_lds, da, db,
+                                      reinterpret_cast<uint32_t *>(sl->ws), ncu, sl->stream);
+            if (e == hipSuccess)
+                e = launch_phase_products(d_pr, (uint32_t)pr.size(), prod_lds, dc, da, db,
+                                          reinterpret_cast<uint64_t *>(sl->ws), ncu, sl->stream);
+            if (e == hipSuccess)
+                e = launch_phase_interp(d_st, d_wso, (uint32_t)st.size(), interp_lds, dc,
+                                        reinterpret_cast<const uint32_t *>(sl->ws), ncu, sl->stream);
+            launches = st.empty() ? 1 : 3;
         }
-        first = last;
-        ++g;
-    }
-    for (int k = 0; fork && e == hipSuccess && k < std::min(g, kSubStreams); ++k) {
-        e = hipEventRecord(sl->join[k], sl->sub[k]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(sl->stream, sl->join[k], 0);
+    } else {
+        DevItem *items = reinterpret_cast<DevItem *>(sl->host);
+        std::vector<DevItem> tmp(count);
+        for (uint32_t i = 0; i < count; ++i)
+            tmp[i] = DevItem{sl->reqs[i].n, kKindCyclic, (uint32_t)cls_of[i], 0u, sl->c_off[i], sl->c_off[i],
+                             sl->c_off[i]};
+        // group by class (largest first) so that each class is one launch
+        std::stable_sort(tmp.begin(), tmp.end(), [](const DevItem &x, const DevItem &y) {
+            return class_info((int)x.cls).S > class_info((int)y.cls).S ||
+                   (class_info((int)x.cls).S == class_info((int)y.cls).S && x.cls < y.cls);
+        });
+        std::memcpy(items, tmp.data(), count * sizeof(DevItem));
+        t_packed = now_ns();
+        e = hipMemcpyAsync(sl->dev, sl->host, count * sizeof(DevItem), hipMemcpyHostToDevice, sl->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(sl->dev + a_at, sl->host + a_at, 2 * off * 8, hipMemcpyHostToDevice, sl->stream);
+        const DevItem *d_items = reinterpret_cast<const DevItem *>(sl->dev);
+        // one launch per class group; with several groups they go to the slot's
+        // sub-streams (forked after the copies, joined before the copy back), a
+        // single group runs on the slot's stream
+        int groups = 0;
+        for (uint32_t i = 0; i < count; ++i) groups += (i == 0 || tmp[i].cls != tmp[i - 1].cls);
+        const bool fork = groups > 1;
+        if (e == hipSuccess && fork) e = hipEventRecord(sl->fork, sl->stream);
+        uint32_t first = 0;
+        int g = 0;
+        char *wp = sl->ws;  // staged groups carve their workspace regions in order
+        while (e == hipSuccess && first < count) {
+            uint32_t last = first;
+            while (last < count && tmp[last].cls == tmp[first].cls) ++last;
+            hipStream_t sub = fork ? sl->sub[g % kSubStreams] : sl->stream;
+            if (fork && g < kSubStreams) e = hipStreamWaitEvent(sub, sl->fork, 0);
+            const int cls = (int)tmp[first].cls;
+            if (e == hipSuccess && class_info(cls).child >= 0) {
+                e = launch_staged(cls, d_items + first, last - first, dc, da, db, wp, srv->ctx->num_cu, sub);
+                wp += round_up(staged_workspace_bytes(cls, last - first), 256);
+            } else if (e == hipSuccess) {
+                e = launch_batched(cls, d_items + first, last - first, dc, da, db, srv->ctx->num_cu, sub);
+            }
+            ++launches;
+            first = last;
+            ++g;
+        }
+        for (int k = 0; fork && e == hipSuccess && k < std::min(g, kSubStreams); ++k) {
+            e = hipEventRecord(sl->join[k], sl->sub[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(sl->stream, sl->join[k], 0);
+        }
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(sl->host + c_at, sl->dev + c_at, off * 8, hipMemcpyDeviceToHost, sl->stream);
     if (e == hipSuccess) e = hipEventRecord(sl->done, sl->stream);
+    const uint64_t t_issued = now_ns();
     if (e != hipSuccess) {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->error = GF2X_EDEVICE;
         srv->error_text = hipGetErrorName(e);
     }
     sl->busy = true;
+    sl->t_admit = t;
+    sl->t_issued = t_issued;
+    sl->phased = phased;
     uint32_t busy = 0;
-    for (const Slot &s : srv->slots) busy += s.busy;
+    for (const Slot &s2 : srv->slots) busy += s2.busy;
     std::lock_guard<std::mutex> lk(srv->mu);
-    srv->stats.batches++;
-    srv->stats.admitted += count;
-    if (count > srv->stats.max_batch_seen) srv->stats.max_batch_seen = count;
-    if (busy > srv->stats.max_slots_busy) srv->stats.max_slots_busy = busy;
+    gf2x_srv_stats &st = srv->stats;
+    st.batches++;
+    st.launches += launches;
+    st.phased_batches += phased;
+    st.admitted += count;
+    if (count > st.max_batch_seen) st.max_batch_seen = count;
+    if (busy > st.max_slots_busy) st.max_slots_busy = busy;
+    st.host_pack_ns += t_packed - t;
+    st.host_pack_max_ns = std::max(st.host_pack_max_ns, t_packed - t);
+    st.host_issue_ns += t_issued - t_packed;
+    st.host_issue_max_ns = std::max(st.host_issue_max_ns, t_issued - t_packed);
     return true;
 }
 
@@ -294,8 +398,17 @@ void scheduler(gf2x_srv *srv) {
     // wake-ups at the requested times.
     prctl(PR_SET_TIMERSLACK, 1UL, 0UL, 0UL, 0UL);
     while (true) {
+        const uint64_t t_iter = now_ns();
         const size_t done = retire(srv);
         const bool launched = launch(srv);
+        {
+            const uint64_t t_end = now_ns(), busy_ns = t_end - t_iter;
+            std::lock_guard<std::mutex> lk(srv->mu);
+            if (busy_ns > srv->stats.loop_busy_max_ns) {
+                srv->stats.loop_busy_max_ns = busy_ns;
+                srv->stats.loop_busy_max_at_ns = t_iter;
+            }
+        }
         if (srv->stop.load()) {
             bool busy = false;
             for (const Slot &s : srv->slots) busy |= s.busy;
@@ -314,7 +427,13 @@ void scheduler(gf2x_srv *srv) {
                 bool any_busy = false;
                 for (const Slot &s : srv->slots) any_busy |= s.busy;
                 if (any_busy) wait_ns = std::min<uint64_t>(wait_ns, kBusyPollNs);
-                if (wait_ns > 2000) srv->cv.wait_for(lk, std::chrono::nanoseconds(wait_ns));
+                if (wait_ns > 2000) {
+                    const uint64_t t_wait = now_ns();
+                    srv->cv.wait_for(lk, std::chrono::nanoseconds(wait_ns));
+                    const uint64_t slept = now_ns() - t_wait;
+                    if (slept > wait_ns)
+                        srv->stats.wake_late_max_ns = std::max(srv->stats.wake_late_max_ns, slept - wait_ns);
+                }
             }
         }
     }
@@ -347,9 +466,15 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
             if (class_info(c).child >= 0) w = std::max(w, staged_workspace_bytes(c, limit));
         return round_up(w + (size_t)kNumClasses * 1024, 256);
     };
+    // descriptors of a phased batch: staged items, two workspace offsets each,
+    // and up to seven point products per staged item plus the direct items
+    auto ph_for = [](uint32_t limit) {
+        return round_up((size_t)limit * (sizeof(DevItem) + 16 + 8 * sizeof(DevItem)) + 3 * 256, 256);
+    };
     uint32_t small_limit = kSmallBatch;
-    while (small_limit > 0 && ws_for(small_limit) * streams * 2 > budget) small_limit /= 2;
-    const size_t ws_bytes = small_limit ? ws_for(small_limit) : 0;
+    while (small_limit > 0 && (ws_for(small_limit) + ph_for(small_limit)) * streams * 2 > budget) small_limit /= 2;
+    const size_t ph_bytes = small_limit ? ph_for(small_limit) : 0;
+    const size_t ws_bytes = small_limit ? ws_for(small_limit) + ph_bytes : 0;  // phase descriptors counted here
     uint64_t max_batch = (budget - ws_bytes * streams) / streams / per_req;
     if (o.max_batch && o.max_batch < max_batch) max_batch = o.max_batch;
     if (max_batch < 1) return GF2X_ENOMEM;  // the budget cannot hold one request per stream
@@ -360,7 +485,8 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
     srv->max_batch = (uint32_t)std::min<uint64_t>(max_batch, 1u << 20);
     srv->max_pending = o.max_pending ? o.max_pending : (1u << 22);
     srv->slot_bytes = round_up((size_t)srv->max_batch * sizeof(DevItem), 256) + 3 * (size_t)srv->max_batch * Wmax * 8;
-    srv->ws_bytes = ws_bytes;
+    srv->ws_bytes = ws_bytes ? ws_bytes - ph_bytes : 0;
+    srv->ph_bytes = ph_bytes;
     srv->small_limit = small_limit;
     srv->slots.resize(streams);
     hipError_t e = hipSetDevice(ctx->device);
@@ -375,6 +501,9 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
         if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.host), srv->slot_bytes, hipHostMallocDefault);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.dev), srv->slot_bytes);
         if (e == hipSuccess && srv->ws_bytes) e = hipMalloc(reinterpret_cast<void **>(&sl.ws), srv->ws_bytes);
+        if (e == hipSuccess && srv->ph_bytes)
+            e = hipHostMalloc(reinterpret_cast<void **>(&sl.ph_host), srv->ph_bytes, hipHostMallocDefault);
+        if (e == hipSuccess && srv->ph_bytes) e = hipMalloc(reinterpret_cast<void **>(&sl.ph_dev), srv->ph_bytes);
     }
     // Touch every page of the slot buffers once, host pages on the CPU and
     // then one copy each way: the first use of fresh pinned and device pages
@@ -385,6 +514,10 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
         std::memset(sl.host, 0, srv->slot_bytes);
         e = hipMemcpyAsync(sl.dev, sl.host, srv->slot_bytes, hipMemcpyHostToDevice, sl.stream);
         if (e == hipSuccess) e = hipMemcpyAsync(sl.host, sl.dev, srv->slot_bytes, hipMemcpyDeviceToHost, sl.stream);
+        if (e == hipSuccess && srv->ph_bytes) {
+            std::memset(sl.ph_host, 0, srv->ph_bytes);
+            e = hipMemcpyAsync(sl.ph_dev, sl.ph_host, srv->ph_bytes, hipMemcpyHostToDevice, sl.stream);
+        }
     }
     for (Slot &sl : srv->slots)
         if (e == hipSuccess) e = hipStreamSynchronize(sl.stream);
@@ -393,7 +526,7 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
         return e == hipErrorOutOfMemory ? GF2X_ENOMEM : GF2X_EDEVICE;
     }
     srv->stats.max_batch = srv->max_batch;
-    srv->stats.hbm_bytes = (srv->slot_bytes + srv->ws_bytes) * streams;
+    srv->stats.hbm_bytes = (srv->slot_bytes + srv->ws_bytes + srv->ph_bytes) * streams;
     srv->thread = std::thread(scheduler, srv);
     *out = srv;
     return GF2X_OK;
@@ -415,7 +548,7 @@ int gf2x_srv_submit(gf2x_srv *srv, uint32_t count, const uint32_t *n_bits, const
         }
         *first_ticket = srv->next_ticket;
         const uint64_t t = now_ns();
-        srv->done_ns.resize(srv->next_ticket + count, 0);
+        srv->done_ns.resize(srv->next_ticket + count - srv->base_ticket, 0);
         for (uint32_t i = 0; i < count; ++i) {
             Request r{n_bits[i], a_base + a_off[i], b_base + b_off[i], c_base + c_off[i],
                       arrival_ns ? arrival_ns[i] : t, srv->next_ticket++};
@@ -429,9 +562,23 @@ int gf2x_srv_submit(gf2x_srv *srv, uint32_t count, const uint32_t *n_bits, const
 
 int gf2x_srv_completion(gf2x_srv *srv, uint64_t first_ticket, uint32_t count, uint64_t *done_ns) {
     if (!srv || (count && !done_ns)) return GF2X_EINVAL;
+    constexpr uint64_t kReturned = (uint64_t)1 << 63;
     std::lock_guard<std::mutex> lk(srv->mu);
-    if (first_ticket + count > srv->done_ns.size()) return GF2X_EINVAL;
-    for (uint32_t i = 0; i < count; ++i) done_ns[i] = srv->done_ns[first_ticket + i];
+    if (first_ticket + count > srv->next_ticket) return GF2X_EINVAL;
+    for (uint32_t i = 0; i < count; ++i) {
+        const uint64_t t = first_ticket + i;
+        if (t < srv->base_ticket) {
+            done_ns[i] = 1;  // completed and read before; its stamp is no longer kept
+            continue;
+        }
+        uint64_t &v = srv->done_ns[t - srv->base_ticket];
+        done_ns[i] = v & ~kReturned;
+        if (v) v |= kReturned;
+    }
+    while (!srv->done_ns.empty() && (srv->done_ns.front() & kReturned)) {
+        srv->done_ns.pop_front();
+        ++srv->base_ticket;
+    }
     return srv->error;
 }
 
@@ -466,6 +613,8 @@ void gf2x_srv_destroy(gf2x_srv *srv) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
         if (sl.dev) (void)hipFree(sl.dev);
         if (sl.ws) (void)hipFree(sl.ws);
+        if (sl.ph_dev) (void)hipFree(sl.ph_dev);
+        if (sl.ph_host) (void)hipHostFree(sl.ph_host);
         if (sl.host) (void)hipHostFree(sl.host);
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.fork) (void)hipEventDestroy(sl.fork);

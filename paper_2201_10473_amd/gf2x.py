@@ -95,6 +95,18 @@ class SrvStats(ctypes.Structure):
         ("max_batch_seen", ctypes.c_uint32),
         ("max_slots_busy", ctypes.c_uint32),
         ("hbm_bytes", ctypes.c_uint64),
+        ("phased_batches", ctypes.c_uint64),
+        ("host_pack_ns", ctypes.c_uint64),
+        ("host_issue_ns", ctypes.c_uint64),
+        ("host_retire_ns", ctypes.c_uint64),
+        ("host_pack_max_ns", ctypes.c_uint64),
+        ("host_issue_max_ns", ctypes.c_uint64),
+        ("host_retire_max_ns", ctypes.c_uint64),
+        ("device_max_ns", ctypes.c_uint64),
+        ("batch_max_ns", ctypes.c_uint64),
+        ("loop_busy_max_ns", ctypes.c_uint64),
+        ("wake_late_max_ns", ctypes.c_uint64),
+        ("loop_busy_max_at_ns", ctypes.c_uint64),
     ]
 
     def as_dict(self):

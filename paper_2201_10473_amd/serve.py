@@ -83,7 +83,8 @@ def run(ctx, rate, count, seed, hbm_budget_bytes=0, streams=0, start_delay_s=0.0
         done = srv.completion(first, count)
         stats = srv.stats()
         if base:  # counters of the timed requests only
-            for k in ("submitted", "admitted", "completed", "batches", "launches"):
+            for k in ("submitted", "admitted", "completed", "batches", "launches", "phased_batches",
+                      "host_pack_ns", "host_issue_ns", "host_retire_ns"):
                 stats[k] -= base[k]
     lat_us = (done.astype(np.int64) - arrival.astype(np.int64)) / 1e3
     span_s = (int(done.max()) - int(arrival.min())) / 1e9
@@ -103,6 +104,8 @@ def run(ctx, rate, count, seed, hbm_budget_bytes=0, streams=0, start_delay_s=0.0
         "p99_us": round(float(np.percentile(lat_us, 99)), 1),
         "per_n": per_n,
         "server": {k: int(v) for k, v in stats.items()},
+        # where the longest scheduler iteration fell: ms after the first arrival
+        "loop_busy_max_at_ms": round((int(stats["loop_busy_max_at_ns"]) - int(arrival.min())) / 1e6, 3),
     }
     return result, (ns, off, A, B, C)
 

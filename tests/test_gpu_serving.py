@@ -40,6 +40,7 @@ def test_served_equals_alone_batched_and_oracle(ctx):
     print("case serving rate=50000 count=3000", flush=True)
     res, (ns, off, A, B, C) = serve.run(ctx, 50000, 3000, inputs.SEED_BASE + 5)
     assert res["server"]["completed"] == 3000 and res["server"]["admitted"] == 3000
+    assert res["server"]["phased_batches"] > 0  # small batches run as three phase kernels
     assert serve.check_against_batched(ctx, ns, off, A, B, C) == 3000
     rng = np.random.default_rng(0)
     for i in rng.choice(3000, 30, replace=False):  # 1% re-run alone
@@ -170,3 +171,23 @@ def test_mixed_workload_graph(ctx):
         for q in pos:
             expect ^= brute.rotate(xa, q, n)
         assert brute.words_to_int(C[sl]) == expect, i
+
+
+def test_completion_stamps_are_released_once_read(ctx):
+    """A stamp is returned once; once every earlier stamp has been returned
+    too, the server drops it and a second read gives 1 (done, not kept)."""
+    ns, off, A, B = serve.make_requests(50, inputs.SEED_BASE + 14)
+    C = np.zeros_like(A)
+    with gf2x.Server(ctx) as srv:
+        first = srv.submit(ns, A, off, B, off, C, off)
+        srv.drain()
+        done = srv.completion(first, 50)
+        assert (done > 1).all()
+        again = srv.completion(first, 50)
+        assert (again == 1).all()
+        second = srv.submit(ns[:5], A, off[:5], B, off[:5], C, off[:5])
+        srv.drain()
+        assert (srv.completion(second, 5) > 1).all()
+        with pytest.raises(gf2x.Gf2xError):
+            srv.completion(second, 6)  # a ticket not yet issued
+    assert ring_mismatches(ns, off, off, off, A, B, C) == []
