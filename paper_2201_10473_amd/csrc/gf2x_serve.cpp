@@ -211,7 +211,7 @@ bool launch(gf2x_srv *srv) {
     uint64_t off = 0;
     const bool small = count <= srv->small_limit && srv->ws_bytes > 0;
     std::vector<int> cls_of(count);
-    bool phased = small;
+    bool phased = true;  // every class the batch needs is held by the phase kernels
     for (uint32_t i = 0; i < count; ++i) {
         const Request &r = sl->reqs[i];
         const uint32_t w32 = (r.n + 31u) / 32u;
@@ -277,18 +277,23 @@ bool launch(gf2x_srv *srv) {
         const size_t st_at = 0, wso_at = round_up(st.size() * sizeof(DevItem), 256);
         const size_t pr_at = wso_at + round_up(wso.size() * 8, 256);
         const size_t ph_used = pr_at + pr.size() * sizeof(DevItem);
-        if (ph_used > srv->ph_bytes || wsw * 4 > srv->ws_bytes) {
-            e = hipErrorInvalidValue;  // cannot happen: both are sized for small_limit requests
+        // a small batch's descriptors go to the phase region; a larger one has
+        // direct classes only (no staged items), in the slot's item region
+        char *dh = small ? sl->ph_host : sl->host;
+        char *dd = small ? sl->ph_dev : sl->dev;
+        const size_t cap = small ? srv->ph_bytes : items_bytes;
+        if (ph_used > cap || wsw * 4 > srv->ws_bytes || (!small && !st.empty())) {
+            e = hipErrorInvalidValue;  // cannot happen: the regions are sized for these batches
         } else {
-            std::memcpy(sl->ph_host + st_at, st.data(), st.size() * sizeof(DevItem));
-            std::memcpy(sl->ph_host + wso_at, wso.data(), wso.size() * 8);
-            std::memcpy(sl->ph_host + pr_at, pr.data(), pr.size() * sizeof(DevItem));
+            std::memcpy(dh + st_at, st.data(), st.size() * sizeof(DevItem));
+            std::memcpy(dh + wso_at, wso.data(), wso.size() * 8);
+            std::memcpy(dh + pr_at, pr.data(), pr.size() * sizeof(DevItem));
             t_packed = now_ns();
-            const DevItem *d_st = reinterpret_cast<const DevItem *>(sl->ph_dev + st_at);
-            const uint64_t *d_wso = reinterpret_cast<const uint64_t *>(sl->ph_dev + wso_at);
-            const DevItem *d_pr = reinterpret_cast<const DevItem *>(sl->ph_dev + pr_at);
+            const DevItem *d_st = reinterpret_cast<const DevItem *>(dd + st_at);
+            const uint64_t *d_wso = reinterpret_cast<const uint64_t *>(dd + wso_at);
+            const DevItem *d_pr = reinterpret_cast<const DevItem *>(dd + pr_at);
             const int ncu = srv->ctx->num_cu;
-            e = hipMemcpyAsync(sl->ph_dev, sl->ph_host, ph_used, hipMemcpyHostToDevice, sl->stream);
+            e = hipMemcpyAsync(dd, dh, ph_used, hipMemcpyHostToDevice, sl->stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(sl->dev + a_at, sl->host + a_at, 2 * off * 8, hipMemcpyHostToDevice, sl->stream);
             if (e == hipSuccess)

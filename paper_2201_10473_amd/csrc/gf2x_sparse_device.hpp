@@ -123,9 +123,11 @@ constexpr uint32_t kSparseMaxBits = 65504;
 constexpr int words_per_lane_needed(uint32_t n) { return (int)((2 * ((n + 31) / 32) + 2 + WAVE - 1) / WAVE); }
 
 // One product: c (W(n) uint64 words) = a (W(n) words, bits >= n ignored) *
-// sum_t X^(pos[t] mod n) mod (X^n - 1), with w positions (uint32) at pos.
-// buf: 64R words of LDS for this wave.  Needs 64 R >= 2 ceil(n/32) + 2.
-template <int R>
+// sum_t X^(pos[t] mod n) mod (X^n - 1), with w positions (uint32) at pos,
+// by NW waves of one workgroup: wave k takes positions k, k + NW, ...; the
+// waves' accumulators are XORed together in LDS.  buf: 64R words of LDS.
+// Needs 64 R >= 2 ceil(n/32) + 2.
+template <int R, int NW>
 __device__ __forceinline__ void product(const uint64_t *a64, const u32 *pos, u32 w, uint64_t *c64, u32 n, u32 *buf) {
     constexpr int WORDS = WAVE * R;
     // q <= ceil(n/32) <= 32 R - 1 (since 64 R >= 2 ceil(n/32) + 2)
@@ -134,6 +136,7 @@ __device__ __forceinline__ void product(const uint64_t *a64, const u32 *pos, u32
     // (words 0 .. ceil(n/32) <= 32 R - 1)
     constexpr int RA = (32 * R - 1) / WAVE + 1;
     const u32 l = lane_id();
+    const u32 wave = NW > 1 ? (u32)threadIdx.x / WAVE : 0u;
     const int w32 = (int)((n + 31u) / 32u);
     const u32 sn = n % 32u;
     const u32 top = sn ? ((1u << sn) - 1u) : 0xFFFFFFFFu;
@@ -161,7 +164,7 @@ __device__ __forceinline__ void product(const uint64_t *a64, const u32 *pos, u32
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0;
 
-    for (u32 t = 0; t < w; ++t) {
+    for (u32 t = wave; t < w; t += NW) {
         const u32 p = mod_n(pos[t], n, M);
         const u32 q = (p + 31u) >> 5;
         const u32 sh = (q << 5) - p;  // a * X^(p + 32) = (a << (32 - sh)) shifted by q words
@@ -175,16 +178,25 @@ __device__ __forceinline__ void product(const uint64_t *a64, const u32 *pos, u32
         for (int r = 0; r < R; ++r) acc[r] ^= X[r];
     }
 
+    // the waves' accumulators into buf
+    if constexpr (NW == 1) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[r * WAVE + (int)l] = acc[r];
+    } else {
+        for (int j = (int)threadIdx.x; j < WORDS; j += NW * WAVE) buf[j] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            __hip_atomic_fetch_xor(&buf[r * WAVE + (int)l], acc[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __syncthreads();
     // fold: the product is acc >> 32 (word j of a * s is word j + 1 of acc);
     // bit k + n of it is added to bit k
-#pragma unroll
-    for (int r = 0; r < R; ++r) buf[r * WAVE + (int)l] = acc[r];
-    __syncthreads();
     const int out32 = 2 * (int)((n + 63u) / 64u);
     const int qn = (int)(n / 32u);
     auto cw = [&](int x) -> u32 { return (x + 1 < WORDS) ? buf[x + 1] : 0u; };
     u32 *c32 = reinterpret_cast<u32 *>(c64);
-    for (int k = (int)l; k < out32; k += WAVE) {
+    for (int k = (int)threadIdx.x; k < out32; k += NW * WAVE) {
         u32 v = 0;
         if (k < w32) {
             v = cw(k) ^ __builtin_amdgcn_alignbit(cw(k + qn + 1), cw(k + qn), sn);

@@ -15,6 +15,8 @@
 thread_local EmuIdx threadIdx;
 
 static pthread_barrier_t g_bar;
+// lane moves (DPP, ds_bpermute) synchronise the 64 lanes of one wave only
+static pthread_barrier_t g_wave_bar[gf2x::NT / 64];
 static uint32_t g_xch[gf2x::NT];
 
 void __syncthreads() { pthread_barrier_wait(&g_bar); }
@@ -41,23 +43,25 @@ unsigned __shfl_xor(unsigned v, int mask, int width) {
 
 int emu_ds_bpermute(int addr, int v) {
     const unsigned t = threadIdx.x;
+    pthread_barrier_t *bar = &g_wave_bar[t / 64u];
     g_xch[t] = (uint32_t)v;
-    pthread_barrier_wait(&g_bar);
+    pthread_barrier_wait(bar);
     const unsigned base = t - t % 64u;
     const int r = (int)g_xch[base + (((unsigned)addr >> 2) & 63u)];
-    pthread_barrier_wait(&g_bar);
+    pthread_barrier_wait(bar);
     return r;
 }
 
 int emu_update_dpp(int old, int v, int ctrl) {
     const unsigned t = threadIdx.x;
+    pthread_barrier_t *bar = &g_wave_bar[t / 64u];
     g_xch[t] = (uint32_t)v;
-    pthread_barrier_wait(&g_bar);
+    pthread_barrier_wait(bar);
     const unsigned base = t - t % 64u, l = t % 64u;
     int r = old;
     if (ctrl == 0x13C) r = (int)g_xch[base + ((l + 63u) & 63u)];       // wave_ror:1
     else if (ctrl == 0x134) r = (int)g_xch[base + ((l + 1u) & 63u)];   // wave_rol:1
-    pthread_barrier_wait(&g_bar);
+    pthread_barrier_wait(bar);
     return r;
 }
 
@@ -286,7 +290,7 @@ extern "C" int emu_staged_words(int which) {
 // words) times the w positions, c = W(n) words.
 namespace {
 struct SparseJob {
-    int which;
+    int which, nw;
     const uint64_t *a;
     const uint32_t *pos;
     uint32_t w, n;
@@ -298,8 +302,11 @@ void *sparse_worker(void *p) {
     SparseJob *j = static_cast<SparseJob *>(p);
     threadIdx.x = j->tid;
     switch (j->which) {
-#define EMU_SPARSE(idx, R) \
-    case idx: gf2x::sparse::product<R>(j->a, j->pos, j->w, j->c, j->n, j->buf); break;
+#define EMU_SPARSE(idx, R)                                                                  \
+    case idx:                                                                               \
+        if (j->nw == 1) gf2x::sparse::product<R, 1>(j->a, j->pos, j->w, j->c, j->n, j->buf); \
+        else gf2x::sparse::product<R, 4>(j->a, j->pos, j->w, j->c, j->n, j->buf);            \
+        break;
         GF2X_SPARSE_LIST(EMU_SPARSE)
         default: break;
     }
@@ -311,20 +318,25 @@ const int kSparseR[] = {GF2X_SPARSE_LIST(EMU_SPARSE_R)};
 
 extern "C" int emu_sparse_words_per_lane(int which) { return kSparseR[which]; }
 
-extern "C" int emu_sparse(int which, const uint64_t *a, const uint32_t *pos, uint32_t w, uint64_t *c, uint32_t n) {
-    if (which < 0 || which >= gf2x::sparse::kSparseClasses) return -1;
+// nw waves (1 or 4) share the positions of one product.
+extern "C" int emu_sparse(int which, int nw, const uint64_t *a, const uint32_t *pos, uint32_t w, uint64_t *c,
+                          uint32_t n) {
+    if (which < 0 || which >= gf2x::sparse::kSparseClasses || (nw != 1 && nw != 4)) return -1;
     if (64 * kSparseR[which] < 2 * (int)((n + 31) / 32) + 2) return -1;
     std::vector<uint32_t> buf(64 * (size_t)kSparseR[which]);
     uint32_t x = 0x9E3779B9u;
     for (auto &v : buf) v = (x = x * 1664525u + 1013904223u);
-    pthread_barrier_init(&g_bar, nullptr, 64);
-    std::vector<pthread_t> th(64);
-    std::vector<SparseJob> jobs(64);
-    for (int t = 0; t < 64; ++t) {
-        jobs[t] = SparseJob{which, a, pos, w, n, c, buf.data(), (unsigned)t};
+    const int threads = 64 * nw;
+    pthread_barrier_init(&g_bar, nullptr, threads);
+    for (int k = 0; k < nw; ++k) pthread_barrier_init(&g_wave_bar[k], nullptr, 64);
+    std::vector<pthread_t> th(threads);
+    std::vector<SparseJob> jobs(threads);
+    for (int t = 0; t < threads; ++t) {
+        jobs[t] = SparseJob{which, nw, a, pos, w, n, c, buf.data(), (unsigned)t};
         pthread_create(&th[t], nullptr, sparse_worker, &jobs[t]);
     }
-    for (int t = 0; t < 64; ++t) pthread_join(th[t], nullptr);
+    for (int t = 0; t < threads; ++t) pthread_join(th[t], nullptr);
     pthread_barrier_destroy(&g_bar);
+    for (int k = 0; k < nw; ++k) pthread_barrier_destroy(&g_wave_bar[k]);
     return 0;
 }

@@ -35,8 +35,8 @@ def emu(tmp_path_factory):
     lib.emu_toeplitz.argtypes = [u64p, ctypes.c_uint32, u64p, u64p, ctypes.c_uint32]
     lib.emu_staged.argtypes = [ctypes.c_int, u64p, u64p, u64p, ctypes.c_uint32, ctypes.c_uint32]
     lib.emu_staged_words.argtypes = [ctypes.c_int]
-    lib.emu_sparse.argtypes = [ctypes.c_int, u64p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32, u64p,
-                               ctypes.c_uint32]
+    lib.emu_sparse.argtypes = [ctypes.c_int, ctypes.c_int, u64p, ctypes.POINTER(ctypes.c_uint32), ctypes.c_uint32,
+                               u64p, ctypes.c_uint32]
     lib.emu_sparse_words_per_lane.argtypes = [ctypes.c_int]
     return lib
 
@@ -108,11 +108,12 @@ def _sparse_dense(pos, n):
     return s
 
 
-@pytest.mark.parametrize("which", range(8))
-def test_sparse_barrel(emu, which):
+@pytest.mark.parametrize("which,nw", [(i, 1) for i in range(8)] + [(1, 4), (6, 4)])
+def test_sparse_barrel(emu, which, nw):
     """Dense x sparse ring product by the rotation barrel, one emulated wave
-    with emulated DPP and ds_bpermute lane moves: the largest and a smaller n
-    of each sparse class, positions that repeat or exceed n, weight 0."""
+    (or four sharing the positions) with emulated DPP and ds_bpermute lane
+    moves: the largest and a smaller n of each sparse class, positions that
+    repeat or exceed n, weight 0."""
     u64p = ctypes.POINTER(ctypes.c_uint64)
     u32p = ctypes.POINTER(ctypes.c_uint32)
     R = emu.emu_sparse_words_per_lane(which)
@@ -124,9 +125,9 @@ def test_sparse_barrel(emu, which):
         for pos in (list(rng.integers(0, n, 5)) + [0, n - 1, n, 0xFFFFFFFF, 7 % n, 7 % n], []):
             p32 = np.asarray(pos, dtype=np.uint32)
             c = np.full(oracle.words(n), 0x5A5A5A5A5A5A5A5A, dtype=np.uint64)
-            rc = emu.emu_sparse(which, a.ctypes.data_as(u64p), p32.ctypes.data_as(u32p), len(p32),
+            rc = emu.emu_sparse(which, nw, a.ctypes.data_as(u64p), p32.ctypes.data_as(u32p), len(p32),
                                 c.ctypes.data_as(u64p), n)
             assert rc == 0
             ref = oracle.mul_cyclic(a & np.append(np.full(len(a) - 1, ~np.uint64(0)), inputs.top_mask(n)),
                                     _sparse_dense(pos, n), n)
-            assert np.array_equal(c, ref), (which, n, len(pos))
+            assert np.array_equal(c, ref), (which, nw, n, len(pos))

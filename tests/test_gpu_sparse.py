@@ -65,6 +65,18 @@ def test_ring_sizes_workload_weights(ctx, n):
         assert brute.words_to_int(C[i]) == expect, i
 
 
+def test_large_batches_one_wave_per_product(ctx):
+    """Batches large enough to fill the device with one wave per product take
+    that kernel (smaller ones let four waves share a product's positions)."""
+    for n, count in ((17669, 4096), (57637, 2048)):
+        w = inputs.sparse_weight_for(n)
+        A = inputs.dense_batch(n, count, SEED + 3, 0)
+        pos_lists = [inputs.sparse_positions(n, w, SEED + 3, i) for i in range(count)]
+        print("case sparse large n=%d count=%d" % (n, count), flush=True)
+        C = _run_sparse(ctx, n, A, pos_lists)
+        _check_all(n, A, pos_lists, C)
+
+
 EDGE = [1, 2, 3, 31, 32, 33, 63, 64, 65, 127, 128, 129, 1000, 4095, 4097, 8160, 8161, 30000, 65503, 65504]
 
 
