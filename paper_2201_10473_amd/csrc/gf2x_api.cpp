@@ -896,6 +896,10 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
                 }
             }
             int best = -1, best_direct = -1, best_single = -1;
+            auto &log = ctx->tune_log[w32];
+            log.clear();
+            for (int c = 0; c < kNumClasses; ++c)
+                if (batch_ms[c] >= 0) log.emplace_back(c, batch_ms[c], single_ms[c]);
             for (int c = 0; c < kNumClasses; ++c) {
                 if (batch_ms[c] >= 0 && (best < 0 || batch_ms[c] < batch_ms[best])) best = c;
                 if (batch_ms[c] >= 0 && class_info(c).child < 0 &&
@@ -929,6 +933,12 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
         for (auto &kv : ctx->tuned)
             std::fprintf(f, "%u %s %s %s\n", kv.first, class_info(kv.second).name,
                          class_info(ctx->direct_of_w32[kv.first]).name, class_info(ctx->single_of_w32[kv.first]).name);
+        // the measurements behind the table, as comments
+        std::fprintf(f, "# candidates: <ceil(n/32)> <class> <ms per batch> <us per single product>\n");
+        for (auto &kv : ctx->tune_log)
+            for (auto &c : kv.second)
+                std::fprintf(f, "# %u %s %.4f %.1f\n", kv.first, class_info(std::get<0>(c)).name, std::get<1>(c),
+                             1000.0f * std::get<2>(c));
         std::fclose(f);
     }
     return GF2X_OK;

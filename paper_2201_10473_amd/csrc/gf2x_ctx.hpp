@@ -71,6 +71,8 @@ struct gf2x_ctx {
     std::map<uint32_t, int> tuned;         // w32 -> class chosen by gf2x_tune or the cache file
     std::map<uint32_t, int> tuned_direct;  // w32 -> fastest direct class measured for that size
     std::map<uint32_t, int> tuned_single;  // w32 -> lowest single-product latency measured
+    // w32 -> every candidate the tuner measured: (class, batch ms, single-product ms)
+    std::map<uint32_t, std::vector<std::tuple<int, float, float>>> tune_log;
     // Device descriptors of single products run in a staged class, one per
     // (n, kind), written once and never overwritten (enqueued work may read
     // them); grown in chunks.

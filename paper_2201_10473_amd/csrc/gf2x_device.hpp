@@ -862,4 +862,272 @@ struct TopT4 {
     }
 };
 
+// --------------------------------------------- Toom-Cook 4 in one workgroup
+// The Toom-Cook 4 level of TopT4 computed inside one workgroup: the seven
+// point products one after another (each by Child, its operands read
+// through TopT4::point_word from the parent's [a | b] in LDS), and the
+// interpolation of TopT4 streamed: the first pass of that interpolation is
+// linear in the point products, so each product is folded into the five
+// numerator arrays U, V, C3, C1, C2 (2m words each) as soon as it exists, and
+// C(0) and C(inf) go straight into the result accumulator R (8m words, in
+// registers: word r is held by thread r mod NT).  Then the four exact
+// divisions and the recomposition of TopT4 run in LDS.
+template <int E, class Top>
+struct T4Source {
+    const u32 *ab;
+    __device__ __forceinline__ u32 get(int x, int w) const {
+        auto part = [&](int xx, int q, int j) -> u32 {
+            return (j >= 0 && j < Top::m) ? ab[xx * Top::S + q * Top::m + j] : 0u;
+        };
+        return Top::point_word(E, x, w, part);
+    }
+};
+
+template <class Child>
+struct SeqT4 {
+    using Top = TopT4<Child>;
+    static constexpr bool IS_SEQ = true;
+    static constexpr int NP = 7;
+    static constexpr int S1 = Child::S;
+    static constexpr int m = S1 - 3;
+    static constexpr int S = 4 * m;
+    static constexpr int L = 2 * m;
+    static constexpr int R_WORDS = 8 * m;
+    static constexpr int IRW = (R_WORDS + NT - 1) / NT;
+    static constexpr int CIN_WORDS = Child::IS_SEQ ? 2 * S1 : 0;
+    static constexpr int TMP_WORDS = 3 * NWAVE;
+    static_assert(Child::SCRATCH >= TMP_WORDS, "child scratch holds the scan scratch");
+    static constexpr int SCRATCH = 5 * L + CIN_WORDS + Child::SCRATCH;
+    static constexpr long long BASE = 7 * Child::BASE;
+    static constexpr long long OPS = Top::OPS;
+
+    // Fold point product e (2*S1 words) into the numerators and R.
+    template <int E>
+    __device__ __forceinline__ static void absorb(const u32 *p, u32 (&R)[IRW], u32 *U, u32 *V, u32 *C3, u32 *C1,
+                                                  u32 *C2) {
+        auto P = [&](int j) -> u32 { return (j >= 0 && j < 2 * S1) ? p[j] : 0u; };
+        const int t = tid();
+        if constexpr (E == 0 || E == 6) {
+            constexpr int at = E == 0 ? 0 : 6 * m;  // c0 at word 0, c6 at word 6m of the product
+#pragma unroll
+            for (int i = 0; i < IRW; ++i) {
+                const int r = t + i * NT;
+                if (r >= at && r < at + L) R[i] ^= P(r - at);
+            }
+        }
+        for (int k = t; k < L; k += NT) {
+            if constexpr (E == 0) {
+                U[k] ^= P(k + 1) ^ P(k - 1) ^ P(k - 3);
+                V[k] ^= P(k + 2) ^ P(k - 4);
+                C3[k] ^= P(k);
+                C2[k] ^= P(k + 2);
+            } else if constexpr (E == 1) {
+                C3[k] ^= P(k);
+            } else if constexpr (E == 2) {
+                U[k] ^= P(k + 1);
+                V[k] ^= P(k + 2);
+                C1[k] ^= P(k + 1);
+                C2[k] ^= P(k + 2);
+            } else if constexpr (E == 3) {
+                U[k] ^= P(k + 1);
+                C1[k] ^= P(k + 1);
+            } else if constexpr (E == 4) {
+                U[k] ^= P(k + 1);
+                V[k] ^= P(k + 2);
+            } else if constexpr (E == 5) {
+                U[k] ^= P(k + 1);
+            } else {
+                const u32 q = P(k + 1) ^ P(k - 1) ^ P(k - 3);
+                U[k] ^= q;
+                V[k] ^= P(k + 2) ^ P(k - 4);
+                C3[k] ^= P(k);
+                C1[k] ^= q;
+                C2[k] ^= P(k - 4);
+            }
+        }
+    }
+
+    template <int E>
+    __device__ __forceinline__ static void point(u32 *ab, u32 (&R)[IRW], u32 *U, u32 *V, u32 *C3, u32 *C1, u32 *C2,
+                                                 u32 *cin, u32 *cs) {
+        const T4Source<E, Top> src{ab};
+        const u32 *p;
+        if constexpr (Child::IS_SEQ) {
+            par_map<2 * S1>(cin, [&](int idx) -> u32 {
+                const int x = idx / S1;
+                return src.get(x, idx - x * S1);
+            });
+            __syncthreads();
+            p = Child::run_ab(cin, cs);
+        } else {
+            p = Child::run_src(src, cs);
+        }
+        absorb<E>(p, R, U, V, C3, C1, C2);
+        __syncthreads();
+    }
+
+    // ab: [a (S) | b (S)] in LDS.  Returns the 2S-word product, written over
+    // ab (whose words are dead once the last point has been evaluated).
+    __device__ __forceinline__ static u32 *run_ab(u32 *ab, u32 *scratch) {
+        u32 *U = scratch;
+        u32 *V = U + L;
+        u32 *C3 = V + L;
+        u32 *C1 = C3 + L;
+        u32 *C2 = C1 + L;
+        u32 *cin = C2 + L;
+        u32 *cs = cin + CIN_WORDS;
+        u32 R[IRW];
+#pragma unroll
+        for (int i = 0; i < IRW; ++i) R[i] = 0;
+        for (int k = tid(); k < 5 * L; k += NT) U[k] = 0;
+        // (the barriers inside the first child run order these stores before any absorb)
+        point<0>(ab, R, U, V, C3, C1, C2, cin, cs);
+        point<1>(ab, R, U, V, C3, C1, C2, cin, cs);
+        point<2>(ab, R, U, V, C3, C1, C2, cin, cs);
+        point<3>(ab, R, U, V, C3, C1, C2, cin, cs);
+        point<4>(ab, R, U, V, C3, C1, C2, cin, cs);
+        point<5>(ab, R, U, V, C3, C1, C2, cin, cs);
+        point<6>(ab, R, U, V, C3, C1, C2, cin, cs);
+        // divisions and recombination, as in TopT4::interp_from
+        u32 *tmp = cs;  // the child's scratch is dead now
+        auto A = [&](const u32 *c, int j) -> u32 { return (j >= 0 && j < L) ? c[j] : 0u; };
+        const int t = tid();
+        scan_xor_stride<L, 3>(U, tmp);
+        for (int k = t; k < L; k += NT) V[k] ^= A(U, k + 1) ^ A(U, k - 3);
+        __syncthreads();
+        scan_xor_stride<L, 2>(V, tmp);
+        for (int k = t; k < L; k += NT) C3[k] ^= U[k] ^ V[k];
+        __syncthreads();
+        for (int k = t; k < L; k += NT)
+            C1[k] ^= A(C3, k + 1) ^ A(C3, k) ^ A(C3, k - 1) ^ A(V, k + 1) ^ A(U, k + 1) ^ A(U, k) ^ A(U, k - 3);
+        __syncthreads();
+        scan_xor_stride<L, 3>(C1, tmp);
+        for (int k = t; k < L; k += NT)
+            C2[k] ^= A(C3, k - 1) ^ A(V, k - 2) ^ A(U, k - 3) ^ A(C1, k + 1) ^ A(C1, k - 3);
+        __syncthreads();
+        scan_xor_stride<L, 2>(C2, tmp);
+#pragma unroll
+        for (int i = 0; i < IRW; ++i) {
+            const int r = t + i * NT;
+            if (r < R_WORDS)
+                ab[r] = R[i] ^ A(C1, r - m) ^ A(C2, r - 2 * m) ^ A(C3, r - 3 * m) ^ A(V, r - 4 * m) ^
+                        A(C2, r - 4 * m) ^ A(U, r - 5 * m) ^ A(C1, r - 5 * m);
+        }
+        __syncthreads();
+        return ab;
+    }
+};
+
+// ------------------------------------- N-way Karatsuba (Appendix A, karat3/5)
+// Operands of S = N S1 words split as a = sum a_i Y^i, Y = X^{32 S1}.  The
+// N(N+1)/2 products P_ii = a_i b_i and P_ij = (a_i + a_j)(b_i + b_j), i < j,
+// give every coefficient: c_k = [k even] P_{k/2,k/2} + sum over i < j with
+// i + j = k of (P_ij + P_ii + P_jj).  So P_ij (i < j) is added at Y^{i+j},
+// and P_ii at Y^{2i} and at Y^{i+j} for every j != i.  The products are
+// computed one after another by Child and added into the result
+// accumulator R (2S words, in registers) as soon as they exist.
+template <int N, class Child>
+struct SeqKN {
+    static constexpr bool IS_SEQ = true;
+    static constexpr int NP = N * (N + 1) / 2;
+    static constexpr int S1 = Child::S;
+    static constexpr int S = N * S1;
+    static constexpr int R_WORDS = 2 * S;
+    static constexpr int IRW = (R_WORDS + NT - 1) / NT;
+    static constexpr int CIN_WORDS = Child::IS_SEQ ? 2 * S1 : 0;
+    static constexpr int SCRATCH = CIN_WORDS + Child::SCRATCH;
+    static constexpr long long BASE = NP * Child::BASE;
+    // evaluation: one XOR per word of the N(N-1)/2 sum operands (2 S1 each);
+    // absorption: N offsets for each P_ii, one for each P_ij, 2 S1 words each
+    static constexpr long long OPS =
+        NP * Child::OPS + (long long)N * (N - 1) * S1 + 2LL * S1 * ((long long)N * N + N * (N - 1) / 2);
+
+    template <int I, int J>
+    struct Src {
+        const u32 *ab;
+        __device__ __forceinline__ u32 get(int x, int w) const {
+            const u32 *o = ab + x * S;
+            if constexpr (I == J) return o[I * S1 + w];
+            else return o[I * S1 + w] ^ o[J * S1 + w];
+        }
+    };
+
+    // P (2 S1 words) added to R at word offset Y^k, for each k with bit k of MASK set
+    template <unsigned MASK>
+    __device__ __forceinline__ static void absorb(const u32 *p, u32 (&R)[IRW]) {
+        const int t = tid();
+#pragma unroll
+        for (int i = 0; i < IRW; ++i) {
+            const int r = t + i * NT;
+            u32 v = 0;
+#pragma unroll
+            for (int k = 0; k < 2 * N - 1; ++k) {
+                if ((MASK >> k) & 1u) {
+                    const int j = r - k * S1;
+                    if (j >= 0 && j < 2 * S1) v ^= p[j];
+                }
+            }
+            if (r < R_WORDS) R[i] ^= v;
+        }
+    }
+
+    template <int I, int J>
+    static constexpr unsigned offsets() {
+        if constexpr (I != J) {
+            return 1u << (I + J);
+        } else {
+            unsigned mk = 1u << (2 * I);
+            for (int j = 0; j < N; ++j)
+                if (j != I) mk |= 1u << (I + j);
+            return mk;
+        }
+    }
+
+    template <int I, int J>
+    __device__ __forceinline__ static void product(u32 *ab, u32 (&R)[IRW], u32 *cin, u32 *cs) {
+        const Src<I, J> src{ab};
+        const u32 *p;
+        if constexpr (Child::IS_SEQ) {
+            par_map<2 * S1>(cin, [&](int idx) -> u32 {
+                const int x = idx / S1;
+                return src.get(x, idx - x * S1);
+            });
+            __syncthreads();
+            p = Child::run_ab(cin, cs);
+        } else {
+            p = Child::run_src(src, cs);
+        }
+        absorb<offsets<I, J>()>(p, R);
+        __syncthreads();
+    }
+
+    template <int I, int J>
+    __device__ __forceinline__ static void products(u32 *ab, u32 (&R)[IRW], u32 *cin, u32 *cs) {
+        if constexpr (I < N) {
+            product<I, J>(ab, R, cin, cs);
+            if constexpr (J + 1 < N) products<I, J + 1>(ab, R, cin, cs);
+            else products<I + 1, I + 1>(ab, R, cin, cs);
+        }
+    }
+
+    // ab: [a (S) | b (S)] in LDS.  Returns the 2S-word product, written over
+    // ab (whose words are dead once the last product has been computed).
+    __device__ __forceinline__ static u32 *run_ab(u32 *ab, u32 *scratch) {
+        u32 *cin = scratch;
+        u32 *cs = cin + CIN_WORDS;
+        u32 R[IRW];
+#pragma unroll
+        for (int i = 0; i < IRW; ++i) R[i] = 0;
+        products<0, 0>(ab, R, cin, cs);
+        const int t = tid();
+#pragma unroll
+        for (int i = 0; i < IRW; ++i) {
+            const int r = t + i * NT;
+            if (r < R_WORDS) ab[r] = R[i];
+        }
+        __syncthreads();
+        return ab;
+    }
+};
+
 }  // namespace gf2x

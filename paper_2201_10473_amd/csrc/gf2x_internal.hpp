@@ -10,8 +10,8 @@
 
 namespace gf2x {
 
-constexpr int kNumDirect = 25;   // classes computed inside one workgroup
-constexpr int kNumClasses = 34;  // plus the staged classes
+constexpr int kNumDirect = 33;   // classes computed inside one workgroup
+constexpr int kNumClasses = 42;  // plus the staged classes
 constexpr uint32_t kKindCyclic = 0;
 constexpr uint32_t kKindFull = 1;
 constexpr uint32_t kKindSparse = 2;  // low byte of the kind; the weight is kind >> 8

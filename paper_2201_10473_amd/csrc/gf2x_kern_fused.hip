@@ -20,7 +20,9 @@ namespace gf2x {
     X(2, 13, Class13)      \
     X(3, 14, Class14)      \
     X(4, 15, Class15)      \
-    X(5, 17, Class17)
+    X(5, 17, Class17)      \
+    X(6, 25, Class25)      \
+    X(7, 26, Class26)
 
 #define GF2X_FUSED_LDS(i, id, T) (lds_words<T>() * 4),
 constexpr int kFusedLdsList[] = {GF2X_FUSED_LIST(GF2X_FUSED_LDS)};

@@ -15,7 +15,8 @@
 namespace gf2x {
 
 // Direct classes of the product phase: the child classes of every staged
-// class, and the direct classes of the six ring sizes.  X(class id, type)
+// class, and the candidate direct classes of the six ring sizes (Toom-3 and
+// Toom-4 over Karatsuba).  X(class id, type)
 #define GF2X_PHASE_LIST(X) \
     X(7, Class7)           \
     X(9, Class9)           \
@@ -27,7 +28,9 @@ namespace gf2x {
     X(21, Class21)         \
     X(22, Class22)         \
     X(23, Class23)         \
-    X(24, Class24)
+    X(24, Class24)         \
+    X(25, Class25)         \
+    X(26, Class26)
 
 // (1) evaluation: staged item i reads its operands from a_base / b_base and
 // writes its point operand pairs at ws + ws_off[2 i] (32-bit words).

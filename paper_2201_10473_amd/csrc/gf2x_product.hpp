@@ -48,6 +48,14 @@ using Class21 = SeqT3<ParK2<5, 7>>;
 using Class22 = SeqT3<ParK2<5, 4>>;
 using Class23 = ParK2<5, 6>;
 using Class24 = ParK2<5, 9>;
+using Class25 = SeqT4<Class24>;
+using Class26 = SeqT4<Class9>;
+using Class27 = SeqT4<Class22>;
+using Class28 = SeqKN<3, Class23>;
+using Class29 = SeqKN<3, Class24>;
+using Class30 = SeqKN<3, Class9>;
+using Class31 = SeqKN<5, Class24>;
+using Class32 = SeqKN<5, Class23>;
 // top levels that exist only as staged classes
 using Top4Class9 = TopT4<Class9>;
 using Top4Class22 = TopT4<Class22>;
@@ -79,7 +87,15 @@ using Top4Class24 = TopT4<Class24>;
     X(21, "T3.K2^5.U7", Class21) \
     X(22, "T3.K2^5.U4", Class22) \
     X(23, "K2^5.U6", Class23) \
-    X(24, "K2^5.U9", Class24)
+    X(24, "K2^5.U9", Class24) \
+    X(25, "T4.K2^5.U9", Class25) \
+    X(26, "T4.T3.K2^5.U5", Class26) \
+    X(27, "T4.T3.K2^5.U4", Class27) \
+    X(28, "K3.K2^5.U6", Class28) \
+    X(29, "K3.K2^5.U9", Class29) \
+    X(30, "K3.T3.K2^5.U5", Class30) \
+    X(31, "K5.K2^5.U9", Class31) \
+    X(32, "K5.K2^5.U6", Class32)
 
 // Staged classes: the top Toom-3 (5 points) or Toom-4 (7 points) level of a
 // class is spread over workgroups.  An evaluation kernel writes the point
@@ -88,15 +104,15 @@ using Top4Class24 = TopT4<Class24>;
 // and folds.
 // X(id, name, top schedule type, child class id, child schedule type)
 #define GF2X_STAGED_LIST(X) \
-    X(25, "G.T3.T3.K2^5.U4", Class14, 22, Class22) \
-    X(26, "G.T3.T3.K2^5.U5", Class15, 9, Class9) \
-    X(27, "G.T3.T3.K2^5.U7", Class17, 21, Class21) \
-    X(28, "G.T3.K2^5.U6", Class10, 23, Class23) \
-    X(29, "G.T3.K2^5.U9", Class13, 24, Class24) \
-    X(30, "G.T3.T3.T3.K2^5.U5", Class20, 15, Class15) \
-    X(31, "G.T4.T3.K2^5.U5", Top4Class9, 9, Class9) \
-    X(32, "G.T4.T3.K2^5.U4", Top4Class22, 22, Class22) \
-    X(33, "G.T4.K2^5.U9", Top4Class24, 24, Class24)
+    X(33, "G.T3.T3.K2^5.U4", Class14, 22, Class22) \
+    X(34, "G.T3.T3.K2^5.U5", Class15, 9, Class9) \
+    X(35, "G.T3.T3.K2^5.U7", Class17, 21, Class21) \
+    X(36, "G.T3.K2^5.U6", Class10, 23, Class23) \
+    X(37, "G.T3.K2^5.U9", Class13, 24, Class24) \
+    X(38, "G.T3.T3.T3.K2^5.U5", Class20, 15, Class15) \
+    X(39, "G.T4.T3.K2^5.U5", Top4Class9, 9, Class9) \
+    X(40, "G.T4.T3.K2^5.U4", Top4Class22, 22, Class22) \
+    X(41, "G.T4.K2^5.U9", Top4Class24, 24, Class24)
 
 #define GF2X_COUNT_CLASS(id, name, T) +1
 constexpr int NUM_CLASSES = 0 GF2X_CLASS_LIST(GF2X_COUNT_CLASS);

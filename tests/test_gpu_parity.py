@@ -111,6 +111,8 @@ ALL_CLASSES = [
     ("T3.T3.K2^5.U5", 1416), ("T3.T3.K2^4.U13", 1848), ("T3.T3.K2^5.U7", 1992), ("T3.T3.K2^5.U10", 2856),
     ("T3.T3.T3.K2^5.U4", 3378), ("T3.T3.T3.K2^5.U5", 4242),
     ("T3.K2^5.U7", 666), ("T3.K2^5.U4", 378), ("K2^5.U6", 192), ("K2^5.U9", 288),
+    ("T4.K2^5.U9", 1140), ("T4.T3.K2^5.U5", 1884), ("T4.T3.K2^5.U4", 1500), ("K3.K2^5.U6", 576),
+    ("K3.K2^5.U9", 864), ("K3.T3.K2^5.U5", 1422), ("K5.K2^5.U9", 1440), ("K5.K2^5.U6", 960),
     ("G.T3.T3.K2^5.U4", 1128), ("G.T3.T3.K2^5.U5", 1416), ("G.T3.T3.K2^5.U7", 1992), ("G.T3.K2^5.U6", 570),
     ("G.T3.K2^5.U9", 858), ("G.T3.T3.T3.K2^5.U5", 4242),
     ("G.T4.T3.K2^5.U5", 1884), ("G.T4.T3.K2^5.U4", 1500), ("G.T4.K2^5.U9", 1140),
