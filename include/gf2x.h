@@ -77,7 +77,7 @@ typedef struct ihipStream_t *gf2x_stream_t;
 #define GF2X_SPARSE_MAX_BITS 65504u
 
 /* Flags for gf2x_mul_batched. */
-#define GF2X_ITEMS_ON_DEVICE 0x1u  /* `items` is a device pointer (not validated on the host)               */
+#define GF2X_ITEMS_ON_DEVICE 0x1u  /* `items` is a device pointer (not validated on the host; see below)     */
 #define GF2X_SHARED_A 0x2u         /* every item has the same a_off and n (one operand shared by the batch) */
 #define GF2X_FORCE_PACKED 0x4u     /* use the bit-packed Karatsuba/Toom path even when GF2X_SHARED_A is set */
 #define GF2X_FORCE_TOEPLITZ 0x8u   /* with GF2X_SHARED_A: use the Toeplitz int8-MFMA path                   */
@@ -209,6 +209,14 @@ int gf2x_plan_launch(gf2x_plan *plan, gf2x_stream_t stream);
 /* Wait for the plan's last replay, then free it and return its device memory
  * to the context's budget.  NULL is accepted.  The context must outlive it. */
 void gf2x_plan_destroy(gf2x_plan *plan);
+
+/* Device-resident descriptors (GF2X_ITEMS_ON_DEVICE) are not validated on the
+ * host; one with n == 0, n > GF2X_MAX_BITS or a kind other than
+ * GF2X_KIND_CYCLIC / GF2X_KIND_FULL is skipped (its output is not written)
+ * and counted on the device.  This call waits for the context's device to
+ * finish its work, returns the number of descriptors skipped since the last
+ * call, and clears the count.  Errors: GF2X_EINVAL, GF2X_EDEVICE. */
+int gf2x_device_item_errors(gf2x_ctx *ctx, uint64_t *count);
 
 /* Schedule the library uses for n: the padded operand size in 32-bit words,
  * the number of 32x32-bit word products computed by the base case, the

@@ -38,6 +38,10 @@ int device_error(hipError_t e) {
 
 uint64_t words64(uint32_t n) { return ((uint64_t)n + 63u) / 64u; }
 
+// In the context's 256-byte counter block: words 0 and 1 are the fused
+// launch's work queue, this word counts skipped device-resident descriptors.
+constexpr int kBadCounter = 16;
+
 }  // namespace
 
 
@@ -581,7 +585,8 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
         if (rc) return rc;
         if (ctx->ws_used) HIP_TRY(hipStreamWaitEvent(s, ctx->ws_free, 0));
         HIP_TRY(launch_convert_items(items, count, ctx->d_items, s));
-        HIP_TRY(launch_mixed(ctx->d_items, count, c_base, a_base, b_base, ctx->d_cls, ctx->num_cu, s));
+        HIP_TRY(launch_mixed(ctx->d_items, count, c_base, a_base, b_base, ctx->d_cls, ctx->d_queue + kBadCounter,
+                             ctx->num_cu, s));
         HIP_TRY(hipEventRecord(ctx->ws_free, s));
         ctx->ws_used = true;
         return GF2X_OK;
@@ -697,6 +702,17 @@ int gf2x_mul_batched_noalloc(gf2x_ctx *ctx, const gf2x_item *items, uint32_t cou
         rc = launch_one(ctx, g, desc, wp, c_base, a_base, b_base, s);
         if (rc) return rc;
     }
+    return GF2X_OK;
+}
+
+int gf2x_device_item_errors(gf2x_ctx *ctx, uint64_t *count) {
+    if (!ctx || !count) return GF2X_EINVAL;
+    HIP_TRY(hipSetDevice(ctx->device));
+    HIP_TRY(hipDeviceSynchronize());
+    uint32_t v = 0;
+    HIP_TRY(hipMemcpy(&v, ctx->d_queue + kBadCounter, 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemset(ctx->d_queue + kBadCounter, 0, 4));
+    *count = v;
     return GF2X_OK;
 }
 

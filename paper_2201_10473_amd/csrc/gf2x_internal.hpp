@@ -106,8 +106,9 @@ hipError_t launch_batched(int cls, const DevItem *items, uint32_t count, uint64_
 hipError_t launch_fill_words(uint64_t *dst, size_t count, uint64_t seed, hipStream_t s);
 hipError_t launch_convert_items(const struct gf2x_item *items, uint32_t count, DevItem *out, hipStream_t s);
 // Items whose classes come from the device table cls_of_w32 (direct classes).
+// Invalid descriptors are skipped and counted in *bad (device memory).
 hipError_t launch_mixed(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
-                        const uint64_t *b_base, const uint8_t *cls_of_w32, int num_cu, hipStream_t s);
+                        const uint64_t *b_base, const uint8_t *cls_of_w32, uint32_t *bad, int num_cu, hipStream_t s);
 
 // Inversion helpers (gf2x_inv.hip): items of W(n) words.
 // out item i = in item i (contiguous) squared j times, inv = 2^(-j) mod n;

@@ -34,15 +34,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(waves_per_si
 // Persistent workgroups over a batch of mixed classes whose items take their
 // class from the per-size table (device-resident descriptors): this kernel
 // computes the items whose class is in group G and skips the others; the
-// host launches the kernel of every group.
+// host launches the kernel of every group.  A descriptor with an invalid n or
+// kind is skipped (its output is not written) and counted in *bad by the
+// group-0 kernel.
 template <int G>
 __global__ __launch_bounds__(NT) void k_mixed(const DevItem *items, u32 count, uint64_t *c_base,
                                               const uint64_t *a_base, const uint64_t *b_base,
-                                              const uint8_t *cls_of_w32) {
+                                              const uint8_t *cls_of_w32, u32 *bad) {
     extern __shared__ u32 smem[];
     for (u32 i = blockIdx.x; i < count; i += gridDim.x) {
         const DevItem it = items[i];
-        if (it.n == 0 || it.n > kMaxBits || it.kind > kKindFull) continue;  // invalid device descriptor
+        if (it.n == 0 || it.n > kMaxBits || it.kind > kKindFull) {  // invalid device descriptor
+            if (G == 0 && tid() == 0) __hip_atomic_fetch_add(bad, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            continue;
+        }
         const u32 cls = (u32)cls_of_w32[(it.n + 31u) / 32u];
         const uint64_t *a = a_base + it.a_off;
         const uint64_t *b = b_base + it.b_off;

@@ -231,14 +231,15 @@ hipError_t launch_convert_items(const gf2x_item *items, uint32_t count, DevItem 
 // One launch per class group, in order on stream s; each skips the items of
 // the other groups.
 hipError_t launch_mixed(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
-                        const uint64_t *b_base, const uint8_t *cls_of_w32, int num_cu, hipStream_t s) {
-    typedef void (*MixedFn)(const DevItem *, u32, uint64_t *, const uint64_t *, const uint64_t *, const uint8_t *);
+                        const uint64_t *b_base, const uint8_t *cls_of_w32, uint32_t *bad, int num_cu, hipStream_t s) {
+    typedef void (*MixedFn)(const DevItem *, u32, uint64_t *, const uint64_t *, const uint64_t *, const uint8_t *,
+                            u32 *);
     for (int g = 0; g < kDirectGroups; ++g) {
         const long long cap = (long long)num_cu * occupancy(kMixed[g], kMixedLds[g]);
         const uint32_t grid = (uint32_t)(count < cap ? count : cap);
         MixedFn fn = reinterpret_cast<MixedFn>(const_cast<void *>(kMixed[g]));
         hipLaunchKernelGGL(fn, dim3(grid), dim3(NT), kMixedLds[g], s, items, count, c_base, a_base, b_base,
-                           cls_of_w32);
+                           cls_of_w32, bad);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

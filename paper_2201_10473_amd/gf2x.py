@@ -145,6 +145,8 @@ def load():
     lib.gf2x_mul_batched.restype = ctypes.c_int
     lib.gf2x_mul_batched_noalloc.argtypes = [vp, vp, u32, vp, vp, vp, vp]
     lib.gf2x_mul_batched_noalloc.restype = ctypes.c_int
+    lib.gf2x_device_item_errors.argtypes = [vp, ctypes.POINTER(u64)]
+    lib.gf2x_device_item_errors.restype = ctypes.c_int
     lib.gf2x_plan_create.argtypes = [ctypes.POINTER(vp), vp, vp, u32, vp, vp, vp, u32]
     lib.gf2x_plan_create.restype = ctypes.c_int
     lib.gf2x_plan_launch.argtypes = [vp, vp]
@@ -272,6 +274,13 @@ class Context:
             ),
             "gf2x_mul_batched",
         )
+
+    def device_item_errors(self):
+        """Device-resident descriptors skipped as invalid since the last call
+        (waits for the device)."""
+        v = ctypes.c_uint64()
+        _check(self._lib.gf2x_device_item_errors(self._h, ctypes.byref(v)), "gf2x_device_item_errors")
+        return v.value
 
     def mul_batched_noalloc(self, items, c_base, a_base, b_base, stream=None):
         """mul_batched with host items, using the library's static scratch

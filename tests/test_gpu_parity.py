@@ -310,6 +310,32 @@ def test_batched_device_items(ctx):
             assert np.array_equal(C[c_off[p]:c_off[p] + 2 * W], ref), p
 
 
+def test_invalid_device_descriptors_are_counted(ctx):
+    """Device-resident descriptors with n = 0, n above the maximum or an
+    unknown kind are skipped (outputs untouched) and counted; the valid ones
+    are computed."""
+    import torch
+    n = 12323
+    W = oracle.words(n)
+    A = inputs.dense_batch(n, 2, SEED + 11, 0)
+    B = inputs.dense_batch(n, 2, SEED + 11, 1)
+    items = gf2x.make_items(np.array([n, 0, n, gf2x.GF2X_MAX_BITS + 1, n], np.uint32),
+                            np.array([0, 0, 7, 0, 0], np.uint32), [0, 0, 0, 0, W], [0, 0, 0, 0, W],
+                            [0, W, 2 * W, 3 * W, 4 * W])
+    d_items = torch.from_numpy(items.view(np.uint8).copy()).cuda()
+    dC = empty_dev(5 * W)
+    ctx.device_item_errors()  # clears any count left by earlier calls
+    ctx.mul_batched(d_items, dC, to_dev(A.ravel()), to_dev(B.ravel()), gf2x.ITEMS_ON_DEVICE, count=5)
+    assert ctx.device_item_errors() == 3
+    assert ctx.device_item_errors() == 0
+    C = from_dev(dC).reshape(5, W)
+    assert np.array_equal(C[0], oracle.mul_cyclic(A[0], B[0], n))
+    assert np.array_equal(C[4], oracle.mul_cyclic(A[1], B[1], n))
+    untouched = np.full(W, 0x5A5A5A5A5A5A5A5A, dtype=np.uint64)
+    for i in (1, 2, 3):
+        assert np.array_equal(C[i], untouched), i
+
+
 def test_mixed_batch_with_sparse_operands(ctx):
     """Mixed sizes, half dense x dense and half dense x sparse, one launch.
     Sparse items are also checked against the rotation closed form."""
