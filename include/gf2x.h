@@ -133,7 +133,8 @@ int gf2x_mul_cyclic(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_
  * the work by decreasing n and copies the descriptors to its workspace;
  * with GF2X_ITEMS_ON_DEVICE the descriptors are used as given and must be
  * valid.  Output ranges of different items must not overlap each other or
- * any operand range.
+ * any operand range (operand ranges may be shared); with host items the
+ * library checks this and returns GF2X_EINVAL.
  * GF2X_SHARED_A (all items share a_off, n and kind == CYCLIC) lets the
  * library pick the Toeplitz MFMA path for that batch; the FORCE flags pin
  * the choice.  GF2X_USE_GRAPH captures the launch sequence in a HIP graph the
@@ -307,6 +308,10 @@ typedef struct gf2x_srv_stats {
     uint64_t host_pack_max_ns, host_issue_max_ns, host_retire_max_ns;
     uint64_t device_max_ns, batch_max_ns, loop_busy_max_ns, wake_late_max_ns;
     uint64_t loop_busy_max_at_ns; /* steady-clock start of the longest scheduler iteration */
+    /* The issue time split by HIP call (maxima over batches): the two
+     * host-to-device copies, the kernel launches (with the sub-stream fork
+     * and join events), the copy back and the completion event. */
+    uint64_t host_issue_copy_max_ns, host_issue_launch_max_ns, host_issue_tail_max_ns;
 } gf2x_srv_stats;
 
 /* Start a server on ctx (which must outlive it).  Errors: GF2X_EINVAL,

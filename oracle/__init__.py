@@ -14,6 +14,8 @@ from .oracle import (  # noqa: F401
     load,
     mul,
     mul_cyclic,
+    mul_batched,
     mul_cyclic_many,
+    REF_ITEM_DTYPE,
     words,
 )

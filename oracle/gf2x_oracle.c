@@ -139,3 +139,55 @@ int gf2x_ref_mul_cyclic_many(uint64_t *r, const uint64_t *a, const uint64_t *b,
     }
     return 0;
 }
+
+/* One product of a batch on host memory: operand a at a_base + a_off, b at
+ * b_base + b_off, result at c_base + c_off (offsets in 64-bit words).  The
+ * kind is 0 (ring product, W(n) result words), 1 (full product, 2 W(n)
+ * words) or 2 + (w << 8): b then holds w positions as 32-bit values from
+ * that offset, the sparse operand being the sum of X^(p mod n) over them
+ * (equal positions cancel), and the result is the ring product with it.
+ * The layout is the batch descriptor of the library's interface, restated
+ * here so that the two share no header. */
+typedef struct {
+    uint32_t n_bits;
+    uint32_t kind;
+    uint64_t a_off, b_off, c_off;
+} gf2x_ref_item;
+
+int gf2x_ref_mul_batched(uint64_t *c_base, const uint64_t *a_base, const uint64_t *b_base,
+                         const gf2x_ref_item *items, uint32_t count)
+{
+    if (count && (!c_base || !a_base || !b_base || !items))
+        return -1;
+    for (uint32_t i = 0; i < count; ++i) {
+        const gf2x_ref_item *it = &items[i];
+        const uint32_t n = it->n_bits;
+        const uint64_t *a = a_base + it->a_off;
+        uint64_t *c = c_base + it->c_off;
+        int rc;
+        if (n == 0)
+            return -1;
+        if (it->kind == 0u) {
+            rc = gf2x_ref_mul_cyclic(c, a, b_base + it->b_off, n);
+        } else if (it->kind == 1u) {
+            rc = gf2x_ref_mul(c, a, b_base + it->b_off, n);
+        } else if ((it->kind & 0xFFu) == 2u) {
+            const uint32_t w = it->kind >> 8;
+            const uint32_t *pos = (const uint32_t *)(b_base + it->b_off);
+            uint64_t *s = (uint64_t *)calloc(WORDS(n), sizeof(uint64_t));
+            if (!s)
+                return -2;
+            for (uint32_t t = 0; t < w; ++t) {
+                const uint32_t p = pos[t] % n;
+                s[p / 64u] ^= (uint64_t)1 << (p % 64u);
+            }
+            rc = gf2x_ref_mul_cyclic(c, a, s, n);
+            free(s);
+        } else {
+            return -1;
+        }
+        if (rc)
+            return rc;
+    }
+    return 0;
+}

@@ -48,6 +48,8 @@ def load():
         lib.gf2x_ref_fold.argtypes = [_u64p, _u64p, ctypes.c_uint32]
         lib.gf2x_ref_mul_cyclic_many.restype = ctypes.c_int
         lib.gf2x_ref_mul_cyclic_many.argtypes = [_u64p, _u64p, _u64p, ctypes.c_uint32, ctypes.c_uint32]
+        lib.gf2x_ref_mul_batched.restype = ctypes.c_int
+        lib.gf2x_ref_mul_batched.argtypes = [_u64p, _u64p, _u64p, ctypes.c_void_p, ctypes.c_uint32]
         lib.gf2x_ref_clmul64.restype = None
         lib.gf2x_ref_clmul64.argtypes = [ctypes.c_uint64, ctypes.c_uint64, _u64p, _u64p]
         _lib = lib
@@ -118,6 +120,36 @@ def mul_cyclic_many(a, b, n):
     if rc:
         raise RuntimeError("gf2x_ref_mul_cyclic_many failed (%d)" % rc)
     return r
+
+
+# One product of a batch: the C oracle's gf2x_ref_item (offsets in uint64
+# words from the base arrays; kind 0 ring, 1 full, 2 + (w << 8) sparse).
+REF_ITEM_DTYPE = np.dtype(
+    [("n_bits", "<u4"), ("kind", "<u4"), ("a_off", "<u8"), ("b_off", "<u8"), ("c_off", "<u8")], align=True
+)
+
+
+def mul_batched(items, c_base, a_base, b_base):
+    """Every product of a batch on host arrays, written into ``c_base`` in
+    place (the items' ranges are checked against the arrays first)."""
+    items = np.ascontiguousarray(items).view(REF_ITEM_DTYPE) if len(items) else np.zeros(0, REF_ITEM_DTYPE)
+    for base in (c_base, a_base, b_base):
+        if not (isinstance(base, np.ndarray) and base.dtype == np.uint64 and base.flags.c_contiguous):
+            raise ValueError("bases must be contiguous uint64 arrays")
+    for it in items:
+        n, kind = int(it["n_bits"]), int(it["kind"])
+        W = words(n)
+        if n == 0 or (kind & 0xFF) > 2 or (kind & 0xFF) != 2 and kind > 1:
+            raise ValueError("bad item %r" % (it,))
+        b_len = ((kind >> 8) + 1) // 2 if kind & 0xFF == 2 else W
+        c_len = 2 * W if kind == 1 else W
+        if (int(it["a_off"]) + W > a_base.size or int(it["b_off"]) + b_len > b_base.size
+                or int(it["c_off"]) + c_len > c_base.size):
+            raise ValueError("item range outside its array: %r" % (it,))
+    rc = load().gf2x_ref_mul_batched(_ptr(c_base), _ptr(a_base), _ptr(b_base), items.ctypes.data, len(items))
+    if rc:
+        raise RuntimeError("gf2x_ref_mul_batched failed (%d)" % rc)
+    return c_base
 
 
 # ------------------------------------------------------------------ inverses

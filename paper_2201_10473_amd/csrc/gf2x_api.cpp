@@ -134,6 +134,56 @@ int check_single(gf2x_ctx *ctx, uint64_t *c, const uint64_t *a, const uint64_t *
     return GF2X_OK;
 }
 
+// Host items of a batch: every output range is disjoint from every other
+// output range and from every operand range (operands may be shared).
+// Output spans are sorted by address (a pass when they already are), so an
+// overlap shows between neighbours; an operand span is checked in O(1) when
+// it lies outside the outputs' hull, else by binary search.  Offsets that
+// would wrap the address space are refused.
+int check_ranges(const gf2x_item *items, uint32_t count, const uint64_t *c_base, const uint64_t *a_base,
+                 const uint64_t *b_base) {
+    struct Span {
+        uintptr_t lo, hi;
+    };
+    thread_local std::vector<Span> outs;
+    outs.resize(count);
+    auto span = [](const void *base, uint64_t off, uint64_t words, Span &sp) -> bool {
+        const uintptr_t b = (uintptr_t)base, room = (UINTPTR_MAX - b) / 8;
+        if (off > room || words > room - off) return false;
+        sp.lo = b + off * 8;
+        sp.hi = sp.lo + words * 8;
+        return true;
+    };
+    bool sorted = true;
+    for (uint32_t i = 0; i < count; ++i) {
+        const gf2x_item &it = items[i];
+        const uint64_t W = words64(it.n_bits);
+        if (!span(c_base, it.c_off, it.kind == GF2X_KIND_FULL ? 2 * W : W, outs[i])) return GF2X_EINVAL;
+        if (i && outs[i].lo < outs[i - 1].lo) sorted = false;
+    }
+    if (!sorted) std::sort(outs.begin(), outs.end(), [](const Span &x, const Span &y) { return x.lo < y.lo; });
+    for (uint32_t i = 1; i < count; ++i)
+        if (outs[i].lo < outs[i - 1].hi) return GF2X_EINVAL;
+    const uintptr_t hull_lo = outs[0].lo, hull_hi = outs[count - 1].hi;
+    auto clash = [&](const Span &sp) -> bool {
+        if (sp.hi <= hull_lo || sp.lo >= hull_hi || sp.lo == sp.hi) return false;
+        // first output span ending after sp.lo (ends increase with starts)
+        auto k = std::upper_bound(outs.begin(), outs.end(), sp.lo,
+                                  [](uintptr_t v, const Span &o) { return v < o.hi; });
+        return k != outs.end() && k->lo < sp.hi;
+    };
+    for (uint32_t i = 0; i < count; ++i) {
+        const gf2x_item &it = items[i];
+        const uint64_t W = words64(it.n_bits);
+        const bool sparse = (it.kind & 0xFFu) == GF2X_KIND_SPARSE;
+        Span sa, sb;
+        if (!span(a_base, it.a_off, W, sa) || !span(b_base, it.b_off, sparse ? ((it.kind >> 8) + 1) / 2 : W, sb))
+            return GF2X_EINVAL;
+        if (clash(sa) || clash(sb)) return GF2X_EINVAL;
+    }
+    return GF2X_OK;
+}
+
 int ensure_items(gf2x_ctx *ctx, size_t count) {
     if (count <= ctx->d_items_cap) return GF2X_OK;
     size_t cap = std::max<size_t>(count, 2 * ctx->d_items_cap);
@@ -176,6 +226,7 @@ uint64_t checksum(const gf2x_item *items, uint32_t count) {
 struct Group {
     int cls;
     uint32_t first, count;
+    int lds = 0;  // fused launch: LDS bytes of its largest class
 };
 
 int build_items(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, std::vector<DevItem> &out,
@@ -202,7 +253,9 @@ int build_items(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, std::vect
         std::stable_sort(out.begin(), out.end(), [](const DevItem &x, const DevItem &y) {
             return class_info((int)x.cls).ops > class_info((int)y.cls).ops;
         });
-        groups.assign(1, Group{kFusedCls, 0, count});
+        int lds = 0;
+        for (const DevItem &d : out) lds = std::max(lds, class_info((int)d.cls).lds_bytes);
+        groups.assign(1, Group{kFusedCls, 0, count, lds});
         return GF2X_OK;
     }
     std::stable_sort(out.begin(), out.end(), [](const DevItem &x, const DevItem &y) {
@@ -267,7 +320,7 @@ int launch_one(gf2x_ctx *ctx, const Group &g, const DevItem *d_items, char *&ws,
                const uint64_t *b, hipStream_t s, uint32_t *queue = nullptr) {
     hipError_t e;
     if (g.cls == kFusedCls) {
-        e = launch_fused(d_items + g.first, g.count, c, a, b, queue, ctx->num_cu, s);
+        e = launch_fused(d_items + g.first, g.count, g.lds, c, a, b, queue, ctx->num_cu, s);
     } else if (class_info(g.cls).child >= 0) {
         e = launch_staged(g.cls, d_items + g.first, g.count, c, a, b, ws, ctx->num_cu, s);
         ws += (staged_workspace_bytes(g.cls, g.count) + 255) / 256 * 256;
@@ -600,6 +653,7 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
                 return GF2X_EINVAL;
         if (items[0].n_bits == 0 || items[0].n_bits > kMaxBits) return GF2X_EINVAL;
         if (flags & GF2X_FORCE_TOEPLITZ) {
+            if (int rc = check_ranges(items, count, c_base, a_base, b_base)) return rc;
             int rc = toeplitz::run(ctx->tz, ctx->budget, ctx->allocated, items, count, c_base, a_base, b_base,
                                    ctx->num_cu, s);
             if (rc == GF2X_EDEVICE) g_last_device_error = toeplitz::last_error();
@@ -625,6 +679,7 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
         std::vector<DevItem> host;
         std::vector<Group> groups;
         int rc = build_items(ctx, items, count, host, groups, fused);
+        if (rc == GF2X_OK) rc = check_ranges(items, count, c_base, a_base, b_base);
         if (rc) return rc;
         while (ctx->graphs.size() >= gf2x_ctx::kMaxGraphs) {
             auto lru = ctx->graphs.begin();
@@ -652,6 +707,7 @@ int gf2x_mul_batched(gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint
     std::vector<DevItem> host;
     std::vector<Group> groups;
     int rc = build_items(ctx, items, count, host, groups, fused);
+    if (rc == GF2X_OK) rc = check_ranges(items, count, c_base, a_base, b_base);
     if (rc) return rc;
     rc = ensure_items(ctx, count);
     if (rc) return rc;
@@ -684,6 +740,7 @@ int gf2x_mul_batched_noalloc(gf2x_ctx *ctx, const gf2x_item *items, uint32_t cou
     thread_local std::vector<DevItem> host;
     thread_local std::vector<Group> groups;
     int rc = build_items(ctx, items, count, host, groups);
+    if (rc == GF2X_OK) rc = check_ranges(items, count, c_base, a_base, b_base);
     if (rc) return rc;
     const size_t cap = kScratchBytes - kScratchItemBytes;
     size_t total = staged_bytes(groups);
@@ -731,6 +788,7 @@ int gf2x_plan_create(gf2x_plan **out, gf2x_ctx *ctx, const gf2x_item *items, uin
         std::vector<DevItem> host;
         std::vector<Group> groups;
         int rc = build_items(ctx, items, count, host, groups, (flags & GF2X_FUSED) != 0);
+        if (rc == GF2X_OK) rc = check_ranges(items, count, c_base, a_base, b_base);
         if (rc == GF2X_OK) rc = record_graph(ctx, host, groups, c_base, a_base, b_base, plan->g, nullptr, false);
         if (rc) {
             delete plan;

@@ -296,6 +296,7 @@ template <int D, int T>
 struct ParK2 {
     static_assert(D >= 0 && pow3(D) <= NT, "one unit per thread");
     static constexpr bool IS_SEQ = false;
+    static constexpr bool FROM_MEM = false;  // operands staged in LDS by the caller
     static constexpr int S = T << D;
     static constexpr long long UNITS = pow3(D);
     // Level D-1 (the units' parents) is stored at a node stride of 4T + 1
@@ -510,9 +511,14 @@ struct EvalSource {
     }
 };
 
-template <class Child>
+// With FROM_MEM, the level reads the parent's operands straight from memory
+// (global, masked to n bits) whenever a point operand is formed, instead of
+// from a copy staged in LDS: the workgroup then needs no LDS for [a | b]
+// (2S words), and the product is assembled in the child's scratch.
+template <class Child, bool MEM = false>
 struct SeqT3 {
     static constexpr bool IS_SEQ = true;
+    static constexpr bool FROM_MEM = MEM;
     static constexpr int NP = 5;  // point products
     static constexpr int S1 = Child::S;
     static constexpr int m = S1 - 2;
@@ -530,6 +536,7 @@ struct SeqT3 {
     // scratch, which is dead by then; the product is written over the
     // operands [a | b] (2S words = R_WORDS), which are dead too.
     static_assert(Child::SCRATCH >= TMP_WORDS, "child scratch holds the scan scratch");
+    static_assert(!MEM || Child::SCRATCH >= R_WORDS + TMP_WORDS, "child scratch holds the product and scan scratch");
     static constexpr int SCRATCH = SA_WORDS + UA_WORDS + CIN_WORDS + Child::SCRATCH;
     static constexpr long long BASE = 5 * Child::BASE;
     // evaluation 16*S1, absorption 30*S1, divisions 4m, recombination 8m
@@ -591,7 +598,35 @@ struct SeqT3 {
 
     template <int E>
     __device__ __forceinline__ static void point(u32 *ab, u32 (&R)[IRW], u32 *Sa, u32 *Ua, u32 *cin, u32 *cs) {
-        const EvalSource<E> src{ab, S, m};
+        point_from<E>(EvalSource<E>{ab, S, m}, R, Sa, Ua, cin, cs);
+    }
+
+    // Word w of operand x of point E from the parent's operands in memory:
+    // part j of operand x is words p m + j of a or b (u32 words), masked to n.
+    template <int E>
+    struct MemSource {
+        const u32 *a, *b;
+        int w32;
+        u32 top;
+        __device__ __forceinline__ u32 part(int x, int p, int j) const {
+            const int k = p * m + j;
+            if (j < 0 || j >= m || k >= w32) return 0u;
+            const u32 v = (x ? b : a)[k];
+            return k == w32 - 1 ? (v & top) : v;
+        }
+        __device__ __forceinline__ u32 get(int x, int w) const {
+            if constexpr (E == 0) return part(x, 0, w);
+            else if constexpr (E == 1) return part(x, 0, w) ^ part(x, 1, w) ^ part(x, 2, w);
+            else if constexpr (E == 2) return part(x, 0, w) ^ part(x, 1, w - 1) ^ part(x, 2, w - 2);
+            else if constexpr (E == 3)
+                return part(x, 0, w) ^ part(x, 1, w) ^ part(x, 2, w) ^ part(x, 1, w - 1) ^ part(x, 2, w - 2);
+            else return part(x, 2, w);
+        }
+    };
+
+    template <int E, class Src>
+    __device__ __forceinline__ static void point_from(const Src &src, u32 (&R)[IRW], u32 *Sa, u32 *Ua, u32 *cin,
+                                                      u32 *cs) {
         const u32 *p;
         if constexpr (Child::IS_SEQ) {
             par_map<2 * S1>(cin, [&](int idx) -> u32 {
@@ -661,6 +696,29 @@ struct SeqT3 {
             case 3: return part(x, 0, w) ^ part(x, 1, w) ^ part(x, 2, w) ^ part(x, 1, w - 1) ^ part(x, 2, w - 2);
             default: return part(x, 2, w);
         }
+    }
+
+    // The parent's operands a, b (n bits each, u32 words) read from memory;
+    // returns the 2S-word product, assembled in the child's scratch.
+    __device__ __forceinline__ static u32 *run_mem(const u32 *a, const u32 *b, u32 n, u32 *scratch) {
+        u32 *Sa = scratch;
+        u32 *Ua = Sa + SA_WORDS;
+        u32 *cin = Ua + UA_WORDS;
+        u32 *cs = cin + CIN_WORDS;
+        const int w32 = (int)((n + 31u) / 32u);
+        const u32 sn = n % 32u;
+        const u32 top = sn ? ((1u << sn) - 1u) : 0xFFFFFFFFu;
+        u32 R[IRW];
+#pragma unroll
+        for (int i = 0; i < IRW; ++i) R[i] = 0;
+        for (int k = tid(); k < SA_WORDS + UA_WORDS; k += NT) Sa[k] = 0;
+        point_from<0>(MemSource<0>{a, b, w32, top}, R, Sa, Ua, cin, cs);
+        point_from<1>(MemSource<1>{a, b, w32, top}, R, Sa, Ua, cin, cs);
+        point_from<2>(MemSource<2>{a, b, w32, top}, R, Sa, Ua, cin, cs);
+        point_from<3>(MemSource<3>{a, b, w32, top}, R, Sa, Ua, cin, cs);
+        point_from<4>(MemSource<4>{a, b, w32, top}, R, Sa, Ua, cin, cs);
+        finish(R, Sa, Ua, cs + R_WORDS, cs);
+        return cs;
     }
 
     // ab: [a (S) | b (S)] in LDS.  Returns the 2S-word product, written over
@@ -760,6 +818,7 @@ __device__ __forceinline__ void scan_xor_stride(u32 *x, u32 *tmp) {
 template <class Child>
 struct TopT4 {
     static constexpr bool IS_SEQ = true;
+    static constexpr bool FROM_MEM = false;
     static constexpr int NP = 7;
     static constexpr int S1 = Child::S;
     static constexpr int m = S1 - 3;
@@ -871,7 +930,9 @@ struct TopT4 {
 // numerator arrays U, V, C3, C1, C2 (2m words each) as soon as it exists, and
 // C(0) and C(inf) go straight into the result accumulator R (8m words, in
 // registers: word r is held by thread r mod NT).  Then the four exact
-// divisions and the recomposition of TopT4 run in LDS.
+// divisions and the recomposition of TopT4 run in LDS.  With MEM, the point
+// operands are formed from the parent's operands in memory (masked to n
+// bits), as in SeqT3: no LDS holds [a | b].
 template <int E, class Top>
 struct T4Source {
     const u32 *ab;
@@ -883,10 +944,28 @@ struct T4Source {
     }
 };
 
-template <class Child>
+// Part q (m words) of operand x read from memory: words q m + j of a or b.
+template <int E, class Top>
+struct T4MemSource {
+    const u32 *a, *b;
+    int w32;
+    u32 top;
+    __device__ __forceinline__ u32 get(int x, int w) const {
+        auto part = [&](int xx, int q, int j) -> u32 {
+            const int k = q * Top::m + j;
+            if (j < 0 || j >= Top::m || k >= w32) return 0u;
+            const u32 v = (xx ? b : a)[k];
+            return k == w32 - 1 ? (v & top) : v;
+        };
+        return Top::point_word(E, x, w, part);
+    }
+};
+
+template <class Child, bool MEM = false>
 struct SeqT4 {
     using Top = TopT4<Child>;
     static constexpr bool IS_SEQ = true;
+    static constexpr bool FROM_MEM = MEM;
     static constexpr int NP = 7;
     static constexpr int S1 = Child::S;
     static constexpr int m = S1 - 3;
@@ -897,6 +976,8 @@ struct SeqT4 {
     static constexpr int CIN_WORDS = Child::IS_SEQ ? 2 * S1 : 0;
     static constexpr int TMP_WORDS = 3 * NWAVE;
     static_assert(Child::SCRATCH >= TMP_WORDS, "child scratch holds the scan scratch");
+    // with MEM the product is written over the child's operands and scratch
+    static_assert(!MEM || CIN_WORDS + Child::SCRATCH >= R_WORDS, "child operands and scratch hold the product");
     static constexpr int SCRATCH = 5 * L + CIN_WORDS + Child::SCRATCH;
     static constexpr long long BASE = 7 * Child::BASE;
     static constexpr long long OPS = Top::OPS;
@@ -947,10 +1028,9 @@ struct SeqT4 {
         }
     }
 
-    template <int E>
-    __device__ __forceinline__ static void point(u32 *ab, u32 (&R)[IRW], u32 *U, u32 *V, u32 *C3, u32 *C1, u32 *C2,
-                                                 u32 *cin, u32 *cs) {
-        const T4Source<E, Top> src{ab};
+    template <int E, class Src>
+    __device__ __forceinline__ static void point(const Src &src, u32 (&R)[IRW], u32 *U, u32 *V, u32 *C3, u32 *C1,
+                                                 u32 *C2, u32 *cin, u32 *cs) {
         const u32 *p;
         if constexpr (Child::IS_SEQ) {
             par_map<2 * S1>(cin, [&](int idx) -> u32 {
@@ -963,6 +1043,36 @@ struct SeqT4 {
             p = Child::run_src(src, cs);
         }
         absorb<E>(p, R, U, V, C3, C1, C2);
+        __syncthreads();
+    }
+
+    // Divisions and recombination, as in TopT4::interp_from; tmp is the
+    // child's scratch (dead now), the 2S-word product goes to out.
+    __device__ __forceinline__ static void finish(const u32 (&R)[IRW], u32 *U, u32 *V, u32 *C3, u32 *C1, u32 *C2,
+                                                  u32 *tmp, u32 *out) {
+        auto A = [&](const u32 *c, int j) -> u32 { return (j >= 0 && j < L) ? c[j] : 0u; };
+        const int t = tid();
+        scan_xor_stride<L, 3>(U, tmp);
+        for (int k = t; k < L; k += NT) V[k] ^= A(U, k + 1) ^ A(U, k - 3);
+        __syncthreads();
+        scan_xor_stride<L, 2>(V, tmp);
+        for (int k = t; k < L; k += NT) C3[k] ^= U[k] ^ V[k];
+        __syncthreads();
+        for (int k = t; k < L; k += NT)
+            C1[k] ^= A(C3, k + 1) ^ A(C3, k) ^ A(C3, k - 1) ^ A(V, k + 1) ^ A(U, k + 1) ^ A(U, k) ^ A(U, k - 3);
+        __syncthreads();
+        scan_xor_stride<L, 3>(C1, tmp);
+        for (int k = t; k < L; k += NT)
+            C2[k] ^= A(C3, k - 1) ^ A(V, k - 2) ^ A(U, k - 3) ^ A(C1, k + 1) ^ A(C1, k - 3);
+        __syncthreads();
+        scan_xor_stride<L, 2>(C2, tmp);  // ends with a barrier: tmp is dead before out is written
+#pragma unroll
+        for (int i = 0; i < IRW; ++i) {
+            const int r = t + i * NT;
+            if (r < R_WORDS)
+                out[r] = R[i] ^ A(C1, r - m) ^ A(C2, r - 2 * m) ^ A(C3, r - 3 * m) ^ A(V, r - 4 * m) ^
+                         A(C2, r - 4 * m) ^ A(U, r - 5 * m) ^ A(C1, r - 5 * m);
+        }
         __syncthreads();
     }
 
@@ -981,40 +1091,44 @@ struct SeqT4 {
         for (int i = 0; i < IRW; ++i) R[i] = 0;
         for (int k = tid(); k < 5 * L; k += NT) U[k] = 0;
         // (the barriers inside the first child run order these stores before any absorb)
-        point<0>(ab, R, U, V, C3, C1, C2, cin, cs);
-        point<1>(ab, R, U, V, C3, C1, C2, cin, cs);
-        point<2>(ab, R, U, V, C3, C1, C2, cin, cs);
-        point<3>(ab, R, U, V, C3, C1, C2, cin, cs);
-        point<4>(ab, R, U, V, C3, C1, C2, cin, cs);
-        point<5>(ab, R, U, V, C3, C1, C2, cin, cs);
-        point<6>(ab, R, U, V, C3, C1, C2, cin, cs);
-        // divisions and recombination, as in TopT4::interp_from
-        u32 *tmp = cs;  // the child's scratch is dead now
-        auto A = [&](const u32 *c, int j) -> u32 { return (j >= 0 && j < L) ? c[j] : 0u; };
-        const int t = tid();
-        scan_xor_stride<L, 3>(U, tmp);
-        for (int k = t; k < L; k += NT) V[k] ^= A(U, k + 1) ^ A(U, k - 3);
-        __syncthreads();
-        scan_xor_stride<L, 2>(V, tmp);
-        for (int k = t; k < L; k += NT) C3[k] ^= U[k] ^ V[k];
-        __syncthreads();
-        for (int k = t; k < L; k += NT)
-            C1[k] ^= A(C3, k + 1) ^ A(C3, k) ^ A(C3, k - 1) ^ A(V, k + 1) ^ A(U, k + 1) ^ A(U, k) ^ A(U, k - 3);
-        __syncthreads();
-        scan_xor_stride<L, 3>(C1, tmp);
-        for (int k = t; k < L; k += NT)
-            C2[k] ^= A(C3, k - 1) ^ A(V, k - 2) ^ A(U, k - 3) ^ A(C1, k + 1) ^ A(C1, k - 3);
-        __syncthreads();
-        scan_xor_stride<L, 2>(C2, tmp);
-#pragma unroll
-        for (int i = 0; i < IRW; ++i) {
-            const int r = t + i * NT;
-            if (r < R_WORDS)
-                ab[r] = R[i] ^ A(C1, r - m) ^ A(C2, r - 2 * m) ^ A(C3, r - 3 * m) ^ A(V, r - 4 * m) ^
-                        A(C2, r - 4 * m) ^ A(U, r - 5 * m) ^ A(C1, r - 5 * m);
-        }
-        __syncthreads();
+        point<0>(T4Source<0, Top>{ab}, R, U, V, C3, C1, C2, cin, cs);
+        point<1>(T4Source<1, Top>{ab}, R, U, V, C3, C1, C2, cin, cs);
+        point<2>(T4Source<2, Top>{ab}, R, U, V, C3, C1, C2, cin, cs);
+        point<3>(T4Source<3, Top>{ab}, R, U, V, C3, C1, C2, cin, cs);
+        point<4>(T4Source<4, Top>{ab}, R, U, V, C3, C1, C2, cin, cs);
+        point<5>(T4Source<5, Top>{ab}, R, U, V, C3, C1, C2, cin, cs);
+        point<6>(T4Source<6, Top>{ab}, R, U, V, C3, C1, C2, cin, cs);
+        finish(R, U, V, C3, C1, C2, cs, ab);
         return ab;
+    }
+
+    // The parent's operands a, b (n bits each, u32 words) read from memory;
+    // returns the 2S-word product, assembled over the child's operands and
+    // scratch.
+    __device__ __forceinline__ static u32 *run_mem(const u32 *a, const u32 *b, u32 n, u32 *scratch) {
+        u32 *U = scratch;
+        u32 *V = U + L;
+        u32 *C3 = V + L;
+        u32 *C1 = C3 + L;
+        u32 *C2 = C1 + L;
+        u32 *cin = C2 + L;
+        u32 *cs = cin + CIN_WORDS;
+        const int w32 = (int)((n + 31u) / 32u);
+        const u32 sn = n % 32u;
+        const u32 top = sn ? ((1u << sn) - 1u) : 0xFFFFFFFFu;
+        u32 R[IRW];
+#pragma unroll
+        for (int i = 0; i < IRW; ++i) R[i] = 0;
+        for (int k = tid(); k < 5 * L; k += NT) U[k] = 0;
+        point<0>(T4MemSource<0, Top>{a, b, w32, top}, R, U, V, C3, C1, C2, cin, cs);
+        point<1>(T4MemSource<1, Top>{a, b, w32, top}, R, U, V, C3, C1, C2, cin, cs);
+        point<2>(T4MemSource<2, Top>{a, b, w32, top}, R, U, V, C3, C1, C2, cin, cs);
+        point<3>(T4MemSource<3, Top>{a, b, w32, top}, R, U, V, C3, C1, C2, cin, cs);
+        point<4>(T4MemSource<4, Top>{a, b, w32, top}, R, U, V, C3, C1, C2, cin, cs);
+        point<5>(T4MemSource<5, Top>{a, b, w32, top}, R, U, V, C3, C1, C2, cin, cs);
+        point<6>(T4MemSource<6, Top>{a, b, w32, top}, R, U, V, C3, C1, C2, cin, cs);
+        finish(R, U, V, C3, C1, C2, cs, cin);
+        return cin;
     }
 };
 
@@ -1029,6 +1143,7 @@ struct SeqT4 {
 template <int N, class Child>
 struct SeqKN {
     static constexpr bool IS_SEQ = true;
+    static constexpr bool FROM_MEM = false;
     static constexpr int NP = N * (N + 1) / 2;
     static constexpr int S1 = Child::S;
     static constexpr int S = N * S1;

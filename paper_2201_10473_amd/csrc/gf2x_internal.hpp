@@ -10,8 +10,8 @@
 
 namespace gf2x {
 
-constexpr int kNumDirect = 33;   // classes computed inside one workgroup
-constexpr int kNumClasses = 42;  // plus the staged classes
+constexpr int kNumDirect = 41;   // classes computed inside one workgroup
+constexpr int kNumClasses = 50;  // plus the staged classes
 constexpr uint32_t kKindCyclic = 0;
 constexpr uint32_t kKindFull = 1;
 constexpr uint32_t kKindSparse = 2;  // low byte of the kind; the weight is kind >> 8
@@ -90,7 +90,7 @@ hipError_t launch_phase_products(const DevItem *items, uint32_t count, int lds, 
 hipError_t launch_phase_interp(const DevItem *items, const uint64_t *ws_off, uint32_t count, int lds,
                                uint64_t *c_base, const uint32_t *ws, int num_cu, hipStream_t s);
 hipError_t prepare_fused_kernel();
-hipError_t launch_fused(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
+hipError_t launch_fused(const DevItem *items, uint32_t count, int lds, uint64_t *c_base, const uint64_t *a_base,
                         const uint64_t *b_base, uint32_t *queue, int num_cu, hipStream_t s);
 hipError_t launch_sparse(int idx, const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
                          const uint64_t *b_base, int num_cu, hipStream_t s);

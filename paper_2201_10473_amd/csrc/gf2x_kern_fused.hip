@@ -2,7 +2,8 @@
 // every workgroup takes the next item from a work queue (items ordered by
 // decreasing cost) and runs the item's direct class, whichever of the fused
 // set it is.  The fused set is the direct classes that the schedule table
-// gives the six ring sizes 12323 ... 57637.
+// gives (or has given) the six ring sizes 12323 ... 57637.  A launch takes
+// the LDS of the largest class it holds.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -22,7 +23,12 @@ namespace gf2x {
     X(4, 15, Class15)      \
     X(5, 17, Class17)      \
     X(6, 25, Class25)      \
-    X(7, 26, Class26)
+    X(7, 26, Class26)      \
+    X(8, 33, Class33)      \
+    X(9, 35, Class35)      \
+    X(10, 36, Class36)     \
+    X(11, 37, Class37)     \
+    X(12, 39, Class39)
 
 #define GF2X_FUSED_LDS(i, id, T) (lds_words<T>() * 4),
 constexpr int kFusedLdsList[] = {GF2X_FUSED_LIST(GF2X_FUSED_LDS)};
@@ -84,12 +90,13 @@ hipError_t prepare_fused_kernel() {
                                kFusedLds);
 }
 
-hipError_t launch_fused(const DevItem *items, uint32_t count, uint64_t *c_base, const uint64_t *a_base,
+hipError_t launch_fused(const DevItem *items, uint32_t count, int lds, uint64_t *c_base, const uint64_t *a_base,
                         const uint64_t *b_base, uint32_t *queue, int num_cu, hipStream_t s) {
-    const long long cap = (long long)num_cu * occupancy(reinterpret_cast<const void *>(&k_fused), kFusedLds);
+    if (lds <= 0 || lds > kFusedLds) return hipErrorInvalidValue;
+    const long long cap = (long long)num_cu * occupancy(reinterpret_cast<const void *>(&k_fused), lds);
     const uint32_t grid = (uint32_t)std::min<long long>(count, cap);
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), kFusedLds, s, items, count, c_base, a_base, b_base, queue);
+    hipLaunchKernelGGL(k_fused, dim3(grid), dim3(NT), lds, s, items, count, c_base, a_base, b_base, queue);
     return hipGetLastError();
 }
 

@@ -30,7 +30,15 @@ namespace gf2x {
     X(23, Class23)         \
     X(24, Class24)         \
     X(25, Class25)         \
-    X(26, Class26)
+    X(26, Class26)         \
+    X(33, Class33)         \
+    X(34, Class34)         \
+    X(35, Class35)         \
+    X(36, Class36)         \
+    X(37, Class37)         \
+    X(38, Class38)         \
+    X(39, Class39)         \
+    X(40, Class40)
 
 // (1) evaluation: staged item i reads its operands from a_base / b_base and
 // writes its point operand pairs at ws + ws_off[2 i] (32-bit words).

@@ -56,6 +56,14 @@ using Class29 = SeqKN<3, Class24>;
 using Class30 = SeqKN<3, Class9>;
 using Class31 = SeqKN<5, Class24>;
 using Class32 = SeqKN<5, Class23>;
+using Class33 = SeqT3<ParK2<5, 6>, true>;
+using Class34 = SeqT3<ParK2<5, 5>, true>;
+using Class35 = SeqT3<ParK2<5, 9>, true>;
+using Class36 = SeqT4<Class24, true>;
+using Class37 = SeqT4<Class9, true>;
+using Class38 = SeqT4<Class22, true>;
+using Class39 = SeqT3<Class9, true>;
+using Class40 = SeqT3<Class22, true>;
 // top levels that exist only as staged classes
 using Top4Class9 = TopT4<Class9>;
 using Top4Class22 = TopT4<Class22>;
@@ -95,7 +103,15 @@ using Top4Class24 = TopT4<Class24>;
     X(29, "K3.K2^5.U9", Class29) \
     X(30, "K3.T3.K2^5.U5", Class30) \
     X(31, "K5.K2^5.U9", Class31) \
-    X(32, "K5.K2^5.U6", Class32)
+    X(32, "K5.K2^5.U6", Class32) \
+    X(33, "T3m.K2^5.U6", Class33) \
+    X(34, "T3m.K2^5.U5", Class34) \
+    X(35, "T3m.K2^5.U9", Class35) \
+    X(36, "T4m.K2^5.U9", Class36) \
+    X(37, "T4m.T3.K2^5.U5", Class37) \
+    X(38, "T4m.T3.K2^5.U4", Class38) \
+    X(39, "T3m.T3.K2^5.U5", Class39) \
+    X(40, "T3m.T3.K2^5.U4", Class40)
 
 // Staged classes: the top Toom-3 (5 points) or Toom-4 (7 points) level of a
 // class is spread over workgroups.  An evaluation kernel writes the point
@@ -104,15 +120,15 @@ using Top4Class24 = TopT4<Class24>;
 // and folds.
 // X(id, name, top schedule type, child class id, child schedule type)
 #define GF2X_STAGED_LIST(X) \
-    X(33, "G.T3.T3.K2^5.U4", Class14, 22, Class22) \
-    X(34, "G.T3.T3.K2^5.U5", Class15, 9, Class9) \
-    X(35, "G.T3.T3.K2^5.U7", Class17, 21, Class21) \
-    X(36, "G.T3.K2^5.U6", Class10, 23, Class23) \
-    X(37, "G.T3.K2^5.U9", Class13, 24, Class24) \
-    X(38, "G.T3.T3.T3.K2^5.U5", Class20, 15, Class15) \
-    X(39, "G.T4.T3.K2^5.U5", Top4Class9, 9, Class9) \
-    X(40, "G.T4.T3.K2^5.U4", Top4Class22, 22, Class22) \
-    X(41, "G.T4.K2^5.U9", Top4Class24, 24, Class24)
+    X(41, "G.T3.T3.K2^5.U4", Class14, 22, Class22) \
+    X(42, "G.T3.T3.K2^5.U5", Class15, 9, Class9) \
+    X(43, "G.T3.T3.K2^5.U7", Class17, 21, Class21) \
+    X(44, "G.T3.K2^5.U6", Class10, 23, Class23) \
+    X(45, "G.T3.K2^5.U9", Class13, 24, Class24) \
+    X(46, "G.T3.T3.T3.K2^5.U5", Class20, 15, Class15) \
+    X(47, "G.T4.T3.K2^5.U5", Top4Class9, 9, Class9) \
+    X(48, "G.T4.T3.K2^5.U4", Top4Class22, 22, Class22) \
+    X(49, "G.T4.K2^5.U9", Top4Class24, 24, Class24)
 
 #define GF2X_COUNT_CLASS(id, name, T) +1
 constexpr int NUM_CLASSES = 0 GF2X_CLASS_LIST(GF2X_COUNT_CLASS);
@@ -121,7 +137,7 @@ constexpr int NUM_STAGED = 0 GF2X_STAGED_LIST(GF2X_COUNT_STAGED);
 static_assert(NUM_CLASSES == kNumDirect && NUM_CLASSES + NUM_STAGED == kNumClasses, "class count mismatch");
 
 template <class Sch>
-constexpr int lds_words() { return 2 * Sch::S + Sch::SCRATCH; }
+constexpr int lds_words() { return (Sch::FROM_MEM ? 0 : 2 * Sch::S) + Sch::SCRATCH; }
 
 // Workgroups of a class that fit in one CU's 160 KB of LDS; with 4 waves per
 // workgroup this is also the number of waves per SIMD the register
@@ -222,9 +238,14 @@ template <class Sch>
 __device__ __forceinline__ void one_product(const uint64_t *a, const uint64_t *b, uint64_t *c, u32 n,
                                             u32 kind, u32 *smem) {
     constexpr int S = Sch::S;
-    stage<S>(a, b, n, smem);
-    __syncthreads();
-    const u32 *R = Sch::run_ab(smem, smem + 2 * S);
+    const u32 *R;
+    if constexpr (Sch::FROM_MEM) {
+        R = Sch::run_mem(reinterpret_cast<const u32 *>(a), reinterpret_cast<const u32 *>(b), n, smem);
+    } else {
+        stage<S>(a, b, n, smem);
+        __syncthreads();
+        R = Sch::run_ab(smem, smem + 2 * S);
+    }
     if (kind == kKindCyclic) store_cyclic<S>(R, n, c);
     else store_full<S>(R, n, c);
     __syncthreads();  // LDS is reused by the next product of a persistent loop

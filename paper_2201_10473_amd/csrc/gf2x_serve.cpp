@@ -236,6 +236,7 @@ bool launch(gf2x_srv *srv) {
     const uint64_t *db = reinterpret_cast<const uint64_t *>(sl->dev + b_at);
     hipError_t e = hipSuccess;
     uint64_t t_packed = now_ns();
+    uint64_t t_copied = 0;
     uint32_t launches = 0;
     if (phased) {
         // three phase kernels: descriptors of the staged items (with their two
@@ -296,6 +297,7 @@ bool launch(gf2x_srv *srv) {
             e = hipMemcpyAsync(dd, dh, ph_used, hipMemcpyHostToDevice, sl->stream);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(sl->dev + a_at, sl->host + a_at, 2 * off * 8, hipMemcpyHostToDevice, sl->stream);
+            t_copied = now_ns();
             if (e == hipSuccess)
                 e = launch_phase_eval(d_st, d_wso, (uint32_t)st.size(), eval_lds, da, db,
                                       reinterpret_cast<uint32_t *>(sl->ws), ncu, sl->stream);
@@ -323,6 +325,7 @@ bool launch(gf2x_srv *srv) {
         e = hipMemcpyAsync(sl->dev, sl->host, count * sizeof(DevItem), hipMemcpyHostToDevice, sl->stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(sl->dev + a_at, sl->host + a_at, 2 * off * 8, hipMemcpyHostToDevice, sl->stream);
+        t_copied = now_ns();
         const DevItem *d_items = reinterpret_cast<const DevItem *>(sl->dev);
         // one launch per class group; with several groups they go to the slot's
         // sub-streams (forked after the copies, joined before the copy back), a
@@ -355,10 +358,12 @@ bool launch(gf2x_srv *srv) {
             if (e == hipSuccess) e = hipStreamWaitEvent(sl->stream, sl->join[k], 0);
         }
     }
+    const uint64_t t_launched = now_ns();
     if (e == hipSuccess)
         e = hipMemcpyAsync(sl->host + c_at, sl->dev + c_at, off * 8, hipMemcpyDeviceToHost, sl->stream);
     if (e == hipSuccess) e = hipEventRecord(sl->done, sl->stream);
     const uint64_t t_issued = now_ns();
+    if (t_copied < t_packed) t_copied = t_packed;  // no copy was issued
     if (e != hipSuccess) {
         std::lock_guard<std::mutex> lk(srv->mu);
         srv->error = GF2X_EDEVICE;
@@ -382,6 +387,9 @@ bool launch(gf2x_srv *srv) {
     st.host_pack_max_ns = std::max(st.host_pack_max_ns, t_packed - t);
     st.host_issue_ns += t_issued - t_packed;
     st.host_issue_max_ns = std::max(st.host_issue_max_ns, t_issued - t_packed);
+    st.host_issue_copy_max_ns = std::max(st.host_issue_copy_max_ns, t_copied - t_packed);
+    st.host_issue_launch_max_ns = std::max(st.host_issue_launch_max_ns, t_launched - t_copied);
+    st.host_issue_tail_max_ns = std::max(st.host_issue_tail_max_ns, t_issued - t_launched);
     return true;
 }
 

@@ -107,6 +107,9 @@ class SrvStats(ctypes.Structure):
         ("loop_busy_max_ns", ctypes.c_uint64),
         ("wake_late_max_ns", ctypes.c_uint64),
         ("loop_busy_max_at_ns", ctypes.c_uint64),
+        ("host_issue_copy_max_ns", ctypes.c_uint64),
+        ("host_issue_launch_max_ns", ctypes.c_uint64),
+        ("host_issue_tail_max_ns", ctypes.c_uint64),
     ]
 
     def as_dict(self):

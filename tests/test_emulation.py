@@ -56,7 +56,7 @@ def _run(lib, cls, n, seed):
 
 # classes 19 and 20 (three Toom-3 levels) take ~15 s each on the CPU and are
 # covered on the GPU by test_every_schedule_class
-@pytest.mark.parametrize("cls", list(range(19)) + list(range(21, 33)))
+@pytest.mark.parametrize("cls", list(range(19)) + list(range(21, 41)))
 def test_class_full_and_ragged(emu, cls):
     S = emu.emu_class_words(cls)
     for n in sorted({S * 32, max(1, S * 32 - 37)}):

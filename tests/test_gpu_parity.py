@@ -113,6 +113,9 @@ ALL_CLASSES = [
     ("T3.K2^5.U7", 666), ("T3.K2^5.U4", 378), ("K2^5.U6", 192), ("K2^5.U9", 288),
     ("T4.K2^5.U9", 1140), ("T4.T3.K2^5.U5", 1884), ("T4.T3.K2^5.U4", 1500), ("K3.K2^5.U6", 576),
     ("K3.K2^5.U9", 864), ("K3.T3.K2^5.U5", 1422), ("K5.K2^5.U9", 1440), ("K5.K2^5.U6", 960),
+    ("T3m.K2^5.U6", 570), ("T3m.K2^5.U5", 474), ("T3m.K2^5.U9", 858),
+    ("T4m.K2^5.U9", 1140), ("T4m.T3.K2^5.U5", 1884), ("T4m.T3.K2^5.U4", 1500), ("T3m.T3.K2^5.U5", 1416),
+    ("T3m.T3.K2^5.U4", 1128),
     ("G.T3.T3.K2^5.U4", 1128), ("G.T3.T3.K2^5.U5", 1416), ("G.T3.T3.K2^5.U7", 1992), ("G.T3.K2^5.U6", 570),
     ("G.T3.K2^5.U9", 858), ("G.T3.T3.T3.K2^5.U5", 4242),
     ("G.T4.T3.K2^5.U5", 1884), ("G.T4.T3.K2^5.U4", 1500), ("G.T4.K2^5.U9", 1140),
@@ -475,3 +478,38 @@ def test_argument_errors(ctx):
         ctx.mul_batched(two, C, A, A, gf2x.SHARED_A)
     assert e.value.code == gf2x.GF2X_EINVAL
     ctx.mul_batched(np.zeros(0, dtype=gf2x.ITEM_DTYPE), C, A, A)  # empty batch is a no-op
+
+
+def test_overlapping_ranges_are_refused(ctx):
+    """Host items: an output range that overlaps another item's output or any
+    operand range is refused with GF2X_EINVAL (shared operands are allowed),
+    on the plain call, the graph path, plans and the allocation-free call."""
+    import torch
+
+    n = 1000
+    W = oracle.words(n)
+    dX = empty_dev(16 * W)
+    ok = gf2x.make_items(n, gf2x.KIND_CYCLIC, 0, 0, [8 * W, 9 * W])  # a, b shared, outputs apart
+    ctx.mul_batched(ok, dX, dX, dX)
+    cases = [
+        gf2x.make_items(n, gf2x.KIND_CYCLIC, 0, 0, [8 * W, 9 * W - 1]),  # outputs overlap by one word
+        gf2x.make_items(n, gf2x.KIND_FULL, 0, 0, [8 * W, 9 * W]),  # full outputs are 2 W words
+        gf2x.make_items(n, gf2x.KIND_CYCLIC, [0, 8 * W + 3], 0, [8 * W, 10 * W]),  # a read from an output
+        gf2x.make_items(n, gf2x.KIND_CYCLIC, 0, [0, 11 * W - 1], [8 * W, 10 * W]),  # b reaches into an output
+        gf2x.make_items(n, gf2x.KIND_CYCLIC, 0, 0, [10 * W, 12 * W, 8 * W, 10 * W + 5]),  # unsorted; 1st and 4th overlap
+        gf2x.make_items(n, gf2x.sparse_kind(5), 0, 10 * W + 2, [8 * W, 10 * W]),  # positions inside an output
+    ]
+    for items in cases:
+        for flags in (0, gf2x.USE_GRAPH):
+            with pytest.raises(gf2x.Gf2xError) as e:
+                ctx.mul_batched(items, dX, dX, dX, flags)
+            assert e.value.code == gf2x.GF2X_EINVAL
+        with pytest.raises(gf2x.Gf2xError) as e:
+            ctx.plan(items, dX, dX, dX)
+        assert e.value.code == gf2x.GF2X_EINVAL
+        with pytest.raises(gf2x.Gf2xError) as e:
+            ctx.mul_batched_noalloc(items, dX, dX, dX)
+        assert e.value.code == gf2x.GF2X_EINVAL
+    # outputs in descending order, apart: accepted
+    ctx.mul_batched(gf2x.make_items(n, gf2x.KIND_CYCLIC, 0, 0, [12 * W, 10 * W, 8 * W]), dX, dX, dX)
+    torch.cuda.synchronize()

@@ -141,6 +141,11 @@ def test_mixed_dense_and_sparse_in_one_batch_and_plan(ctx):
         n = int(ns[i])
         Bref[off[i]:off[i] + W[i]] = dense_of_positions(pos_lists[j], n)
     from tests.oracle_check import ring_mismatches
+    # the oracle's batched entry point on the same descriptors and buffers
+    # (the first 96 items), beside the threaded per-item check below
+    Cref = np.zeros(len(A), dtype=np.uint64)
+    oracle.mul_batched(items[:96], Cref, A, B)
+    head = int(off[96])
     for how in ("call", "graph", "plan"):
         dC = empty_dev(len(A))
         print("case mixed dense and sparse: %s" % how, flush=True)
@@ -156,4 +161,5 @@ def test_mixed_dense_and_sparse_in_one_batch_and_plan(ctx):
                 torch.cuda.synchronize()
         torch.cuda.synchronize()
         C = from_dev(dC)
+        assert np.array_equal(C[:head], Cref[:head]), how
         assert ring_mismatches(ns, off, off, off, A, Bref, C) == [], how

@@ -238,6 +238,60 @@ def test_mul_cyclic_many_matches_single():
         assert np.array_equal(R[i], oracle.mul_cyclic(A[i], B[i], n))
 
 
+def test_mul_batched_matches_bit_loops():
+    """The batched entry point on host arrays: ring, full and sparse items of
+    tiny mixed sizes against the bit-by-bit definitions (the sparse operand
+    as the sum of the rotations of a over its positions, equal positions
+    cancelling), with shared operands and outputs in arbitrary order."""
+    rng = random.Random(2201)
+    sizes = [1, 5, 63, 64, 65, 127, 130, 200]
+    A = np.zeros(512, dtype=np.uint64)
+    B = np.zeros(512, dtype=np.uint64)
+    for i in range(A.size):
+        A[i] = rng.getrandbits(64)
+        B[i] = rng.getrandbits(64)
+    items, expect, c_off = [], [], 0
+    for k in range(24):
+        n = sizes[k % len(sizes)]
+        W = oracle.words(n)
+        kind = k % 3
+        a_off, b_off = rng.randrange(0, 32), rng.randrange(0, 32)
+        xa = brute.words_to_int(A[a_off:a_off + W]) & ((1 << n) - 1)
+        if kind == 2:
+            pos = [rng.randrange(0, 3 * n) for _ in range(rng.randrange(0, 9))]
+            if k % 2:
+                q = rng.randrange(0, n)
+                pos += [q, q + n]  # equal modulo n: they cancel
+            w = len(pos)
+            b_off = 128 + 8 * k
+            B[b_off:b_off + (w + 1) // 2] = 0
+            B[b_off:b_off + (w + 1) // 2].view(np.uint32)[:w] = pos
+            r = 0
+            for p in pos:
+                r ^= brute.rotate(xa, p % n, n)
+            items.append((n, 2 | (w << 8), a_off, b_off, c_off))
+            expect.append((c_off, brute.int_to_words(r, W)))
+            c_off += W
+        else:
+            xb = brute.words_to_int(B[b_off:b_off + W]) & ((1 << n) - 1)
+            if kind == 0:
+                r, cw = brute.cyclic_bitloop(xa, xb, n), W
+            else:
+                r, cw = brute.clmul_bitloop(xa, xb), 2 * W
+            items.append((n, kind, a_off, b_off, c_off))
+            expect.append((c_off, brute.int_to_words(r, cw)))
+            c_off += cw
+    arr = np.array(items[::-1], dtype=oracle.REF_ITEM_DTYPE)
+    C = np.full(c_off, 0xA5A5A5A5A5A5A5A5, dtype=np.uint64)
+    oracle.mul_batched(arr, C, A, B)
+    for off, e in expect:
+        assert np.array_equal(C[off:off + e.size], e), off
+    with pytest.raises(ValueError):
+        oracle.mul_batched(np.array([(100, 0, 0, 0, C.size)], dtype=oracle.REF_ITEM_DTYPE), C, A, B)
+    with pytest.raises(ValueError):
+        oracle.mul_batched(np.array([(100, 3, 0, 0, 0)], dtype=oracle.REF_ITEM_DTYPE), C, A, B)
+
+
 # ---------------------------------------------------------------- mutation check
 # Each mutant plants one plausible mistake in a private copy of the oracle
 # source; the pins above must reject every one of them.
