@@ -10,10 +10,14 @@
  *   - Section 1 (circulant matrices and the ring F2[X]/(X^N - 1)): the
  *     code-based KEMs need that product reduced modulo X^n - 1, i.e. bit k+n
  *     of the full product is added to bit k.
- *   - Appendix A (Karatsuba 2-, 3- and 5-way splits) and Section 3 with
+ *   - Appendix A (Karatsuba 2-, 3- and 5-way splits), Section 3 with
  *     Appendix D (word-aligned Toom-Cook 3 with evaluation points 0, 1, x,
- *     x+1, infinity and exact divisions by x and x+1) are the recursions the
- *     GPU kernels use; the result does not depend on which one is chosen.
+ *     x+1, infinity and exact divisions by x and x+1) and the Toom-Cook 4
+ *     split of Section 3 (7 products) are the recursions the GPU kernels
+ *     implement; a measured per-size table picks among them, and the result
+ *     does not depend on the choice.
+ *   - Section 1 (sparse-dense products of HQC and BIKE): a dense operand
+ *     times a sparse one given by its positions (GF2X_SPARSE_KIND below).
  *
  * Layout.  A polynomial of n coefficients occupies W(n) = ceil(n/64)
  * uint64 words, little-endian: coefficient i is bit (i mod 64) of word
@@ -28,12 +32,15 @@
  * stream has passed the call.
  *
  * Streams and synchronisation.  Calls enqueue work on the given HIP stream
- * (NULL = the default stream) and return; they never wait for the device and
- * never read device memory from the host.  One context may be used from one
- * host thread at a time.
+ * (NULL = the default stream) and return; they do not wait for the device,
+ * except where a call says so (the tuner, plan creation and destruction,
+ * gf2x_device_item_errors, the server's drain, and the growth of a
+ * workspace, which waits for its previous user).  One context may be used
+ * from one host thread at a time.
  *
  * Constant time.  Control flow, loop bounds and every memory address inside
- * the kernels depend only on n (public); never on operand bits.
+ * the kernels depend only on n (public) and, for dense x sparse items, on the
+ * weight w (public); never on operand bits or sparse positions.
  *
  * Errors.  Every entry point returns 0 on success or a negative GF2X_E* code;
  * no exception crosses the ABI.  On error nothing has been enqueued.

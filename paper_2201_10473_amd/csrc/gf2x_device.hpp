@@ -3,18 +3,23 @@
 //
 // Words are 32 bits on the device (the VALU word); a polynomial of S words
 // holds coefficient i in bit (i mod 32) of word floor(i/32).  One workgroup
-// of NT threads computes one product with every operand, partial product
-// and accumulator resident in LDS.
+// of NT threads computes one product with its partial products and
+// accumulators in LDS and registers.
 //
-// The recursion is a compile-time schedule built from three pieces:
+// The recursion is a compile-time schedule built from these pieces:
 //   * unit_mul<T>      -- T x T word schoolbook product held in one thread's
 //                         registers (the base case).
 //   * ParK2<D, T>      -- D levels of 2-way Karatsuba (Appendix A, KaratRec),
 //                         executed breadth first: all 3^D base products of a
 //                         level run at once, one per thread.
-//   * SeqT3<Child>     -- word-aligned Toom-Cook 3 (Appendix D, Section 3.2)
+//   * SeqT3<Child,MEM> -- word-aligned Toom-Cook 3 (Appendix D, Section 3.2)
 //                         with w = 32, whose five point products are computed
 //                         one after another by Child (saves LDS).
+//   * SeqT4<Child,MEM> -- Toom-Cook 4 (Section 3, seven products), the same
+//                         way; TopT4<Child> is its form spread over workgroups.
+//   * SeqKN<N, Child>  -- 3- and 5-way Karatsuba (Appendix A, karat3/karat5).
+// With MEM, a Toom level reads the parent's operands from global memory
+// whenever it forms a point operand, so no LDS holds them.
 //
 // Constant time: every loop bound, branch and LDS/global address depends
 // only on the compile-time schedule, the thread index and the public n --

@@ -80,14 +80,18 @@ hipError_t scratch_for_device(int device, void **ptr) {
      T::OPS, c, -2, T::NP},
 static ClassInfo kClassInfo[] = {GF2X_CLASS_LIST(GF2X_INFO) GF2X_STAGED_LIST(GF2X_STAGED_INFO)};
 
-// The direct class of a staged class is the one with the same top schedule;
-// a top level that exists only staged (Toom-4) takes the cheapest direct
-// class that holds its size.
+// The direct class of a staged class is one with the same top schedule (the
+// one with the least LDS when a from-memory form exists); a top level without
+// such a class takes the cheapest direct class that holds its size.
 static int find_direct(int id) {
     const ClassInfo &ci = kClassInfo[id];
     if (ci.direct != -2) return ci.direct;
+    int same = -1;
     for (int c = 0; c < kNumDirect; ++c)
-        if (kClassInfo[c].S == ci.S && kClassInfo[c].ops == ci.ops) return c;
+        if (kClassInfo[c].S == ci.S && kClassInfo[c].ops == ci.ops &&
+            (same < 0 || kClassInfo[c].lds_bytes < kClassInfo[same].lds_bytes))
+            same = c;
+    if (same >= 0) return same;
     int best = -1;
     for (int c = 0; c < kNumDirect; ++c)
         if (kClassInfo[c].S >= ci.S && (best < 0 || kClassInfo[c].ops < kClassInfo[best].ops)) best = c;
