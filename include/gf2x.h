@@ -281,11 +281,14 @@ int gf2x_tune(gf2x_ctx *ctx, const uint32_t *sizes, uint32_t nsizes, uint32_t ba
  * on the device.  A batch of at most 256 requests runs each product in its
  * size's lowest-latency class (possibly staged, using a per-slot workspace
  * within half of the budget; with many streams or a small budget the limit
- * is halved until the workspaces fit, down to none), as three phase kernels
- * for all of its sizes (evaluations, one-workgroup products, interpolations)
- * when every class it needs is one the phase kernels hold; larger batches run
- * one workgroup per product, one launch per size class.  Results are identical to gf2x_mul_cyclic of the
- * same operands (every class computes the same exact product). */
+ * is halved until the workspaces fit, down to none); larger batches run
+ * each product in its size's fastest one-workgroup class.  A batch whose
+ * classes the phase kernels hold runs as three launches for all of its sizes
+ * (evaluations, one-workgroup products, interpolations), else one launch per
+ * size class.  Operands and descriptors reach the device, and results the
+ * pinned buffer, through copy kernels (no DMA copy call per batch).  Results
+ * are identical to gf2x_mul_cyclic of the same operands (every class
+ * computes the same exact product). */
 typedef struct gf2x_srv gf2x_srv;
 
 typedef struct gf2x_srv_opts {
@@ -315,9 +318,11 @@ typedef struct gf2x_srv_stats {
     uint64_t host_pack_max_ns, host_issue_max_ns, host_retire_max_ns;
     uint64_t device_max_ns, batch_max_ns, loop_busy_max_ns, wake_late_max_ns;
     uint64_t loop_busy_max_at_ns; /* steady-clock start of the longest scheduler iteration */
-    /* The issue time split by HIP call (maxima over batches): the two
-     * host-to-device copies, the kernel launches (with the sub-stream fork
-     * and join events), the copy back and the completion event. */
+    /* The issue time split by HIP call (maxima over batches): the copy in
+     * (a kernel that reads the descriptors and operands out of the pinned
+     * buffer), the product kernel launches (with any sub-stream fork and
+     * join events), the copy back (a kernel that writes the results into the
+     * pinned buffer) and the completion event. */
     uint64_t host_issue_copy_max_ns, host_issue_launch_max_ns, host_issue_tail_max_ns;
 } gf2x_srv_stats;
 

@@ -23,6 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 
 # the heaviest translation units first, so that they start first
 SOURCES = [
+    "gf2x_copy.hip",
     "gf2x_kern_phase.hip",
     "gf2x_kern_fused.hip",
     "gf2x_kern_staged.hip",

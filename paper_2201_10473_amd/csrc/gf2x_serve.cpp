@@ -41,6 +41,7 @@
 #include <vector>
 
 #include "gf2x.h"
+#include "gf2x_copy.hpp"
 #include "gf2x_ctx.hpp"
 #include "gf2x_internal.hpp"
 
@@ -82,9 +83,11 @@ struct Slot {
     hipStream_t sub[kSubStreams] = {};   // class groups of one batch run side by side
     hipEvent_t fork = nullptr, join[kSubStreams] = {};
     char *host = nullptr;   // pinned: [items | a | b | c]
+    char *host_dev = nullptr;  // the device's view of host
     char *dev = nullptr;    // device: same layout
     char *ws = nullptr;     // device workspace of the staged groups of a small batch
     char *ph_host = nullptr, *ph_dev = nullptr;  // descriptors of a phased batch (pinned, device)
+    char *ph_host_dev = nullptr;                 // the device's view of ph_host
     std::vector<Request> reqs;
     std::vector<uint64_t> c_off;  // word offset of each request's result in the c region
     size_t c_region = 0;          // byte offset of the c region
@@ -281,6 +284,7 @@ bool launch(gf2x_srv *srv) {
         // a small batch's descriptors go to the phase region; a larger one has
         // direct classes only (no staged items), in the slot's item region
         char *dh = small ? sl->ph_host : sl->host;
+        const char *dh_dev = small ? sl->ph_host_dev : sl->host_dev;
         char *dd = small ? sl->ph_dev : sl->dev;
         const size_t cap = small ? srv->ph_bytes : items_bytes;
         if (ph_used > cap || wsw * 4 > srv->ws_bytes || (!small && !st.empty())) {
@@ -294,9 +298,11 @@ bool launch(gf2x_srv *srv) {
             const uint64_t *d_wso = reinterpret_cast<const uint64_t *>(dd + wso_at);
             const DevItem *d_pr = reinterpret_cast<const DevItem *>(dd + pr_at);
             const int ncu = srv->ctx->num_cu;
-            e = hipMemcpyAsync(dd, dh, ph_used, hipMemcpyHostToDevice, sl->stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(sl->dev + a_at, sl->host + a_at, 2 * off * 8, hipMemcpyHostToDevice, sl->stream);
+            // descriptors and operands pulled from the pinned buffers by one
+            // kernel (no DMA copy call; sizes are multiples of 8 bytes)
+            e = launch_pull(reinterpret_cast<const uint64_t *>(dh_dev), reinterpret_cast<uint64_t *>(dd), ph_used / 8,
+                            reinterpret_cast<const uint64_t *>(sl->host_dev + a_at),
+                            reinterpret_cast<uint64_t *>(sl->dev + a_at), 2 * off, sl->stream);
             t_copied = now_ns();
             if (e == hipSuccess)
                 e = launch_phase_eval(d_st, d_wso, (uint32_t)st.size(), eval_lds, da, db,
@@ -322,9 +328,9 @@ bool launch(gf2x_srv *srv) {
         });
         std::memcpy(items, tmp.data(), count * sizeof(DevItem));
         t_packed = now_ns();
-        e = hipMemcpyAsync(sl->dev, sl->host, count * sizeof(DevItem), hipMemcpyHostToDevice, sl->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(sl->dev + a_at, sl->host + a_at, 2 * off * 8, hipMemcpyHostToDevice, sl->stream);
+        e = launch_pull(reinterpret_cast<const uint64_t *>(sl->host_dev), reinterpret_cast<uint64_t *>(sl->dev),
+                        count * sizeof(DevItem) / 8, reinterpret_cast<const uint64_t *>(sl->host_dev + a_at),
+                        reinterpret_cast<uint64_t *>(sl->dev + a_at), 2 * off, sl->stream);
         t_copied = now_ns();
         const DevItem *d_items = reinterpret_cast<const DevItem *>(sl->dev);
         // one launch per class group; with several groups they go to the slot's
@@ -360,7 +366,8 @@ bool launch(gf2x_srv *srv) {
     }
     const uint64_t t_launched = now_ns();
     if (e == hipSuccess)
-        e = hipMemcpyAsync(sl->host + c_at, sl->dev + c_at, off * 8, hipMemcpyDeviceToHost, sl->stream);
+        e = launch_push(reinterpret_cast<const uint64_t *>(sl->dev + c_at),
+                        reinterpret_cast<uint64_t *>(sl->host_dev + c_at), off, sl->stream);
     if (e == hipSuccess) e = hipEventRecord(sl->done, sl->stream);
     const uint64_t t_issued = now_ns();
     if (t_copied < t_packed) t_copied = t_packed;  // no copy was issued
@@ -511,26 +518,34 @@ int gf2x_srv_create(gf2x_srv **out, gf2x_ctx *ctx, const gf2x_srv_opts *opts) {
             e = hipStreamCreateWithFlags(&sl.sub[k], hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.join[k], hipEventDisableTiming);
         }
-        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.host), srv->slot_bytes, hipHostMallocDefault);
+        // coherent pinned memory: the pull kernel reads it over PCIe on every
+        // batch, so no device cache may hold a line of an earlier batch
+        const unsigned pin = hipHostMallocMapped | hipHostMallocCoherent;
+        if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&sl.host), srv->slot_bytes, pin);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&sl.dev), srv->slot_bytes);
         if (e == hipSuccess && srv->ws_bytes) e = hipMalloc(reinterpret_cast<void **>(&sl.ws), srv->ws_bytes);
         if (e == hipSuccess && srv->ph_bytes)
-            e = hipHostMalloc(reinterpret_cast<void **>(&sl.ph_host), srv->ph_bytes, hipHostMallocDefault);
+            e = hipHostMalloc(reinterpret_cast<void **>(&sl.ph_host), srv->ph_bytes, pin);
         if (e == hipSuccess && srv->ph_bytes) e = hipMalloc(reinterpret_cast<void **>(&sl.ph_dev), srv->ph_bytes);
+        if (e == hipSuccess) e = hipHostGetDevicePointer(reinterpret_cast<void **>(&sl.host_dev), sl.host, 0);
+        if (e == hipSuccess && srv->ph_bytes)
+            e = hipHostGetDevicePointer(reinterpret_cast<void **>(&sl.ph_host_dev), sl.ph_host, 0);
     }
     // Touch every page of the slot buffers once, host pages on the CPU and
-    // then one copy each way: the first use of fresh pinned and device pages
-    // is slower than later uses and would otherwise land on the requests of
-    // the first large batches.
+    // then once each way from the device, through the same pull kernel and
+    // copy back as a batch: the first use of fresh pinned and device pages is
+    // slower than later uses and would otherwise land on the requests of the
+    // first large batches.
     for (Slot &sl : srv->slots) {
         if (e != hipSuccess) break;
         std::memset(sl.host, 0, srv->slot_bytes);
-        e = hipMemcpyAsync(sl.dev, sl.host, srv->slot_bytes, hipMemcpyHostToDevice, sl.stream);
-        if (e == hipSuccess) e = hipMemcpyAsync(sl.host, sl.dev, srv->slot_bytes, hipMemcpyDeviceToHost, sl.stream);
-        if (e == hipSuccess && srv->ph_bytes) {
-            std::memset(sl.ph_host, 0, srv->ph_bytes);
-            e = hipMemcpyAsync(sl.ph_dev, sl.ph_host, srv->ph_bytes, hipMemcpyHostToDevice, sl.stream);
-        }
+        if (srv->ph_bytes) std::memset(sl.ph_host, 0, srv->ph_bytes);
+        e = launch_pull(reinterpret_cast<const uint64_t *>(sl.host_dev), reinterpret_cast<uint64_t *>(sl.dev),
+                        srv->slot_bytes / 8, reinterpret_cast<const uint64_t *>(sl.ph_host_dev),
+                        reinterpret_cast<uint64_t *>(sl.ph_dev), srv->ph_bytes / 8, sl.stream);
+        if (e == hipSuccess)
+            e = launch_push(reinterpret_cast<const uint64_t *>(sl.dev), reinterpret_cast<uint64_t *>(sl.host_dev),
+                            srv->slot_bytes / 8, sl.stream);
     }
     for (Slot &sl : srv->slots)
         if (e == hipSuccess) e = hipStreamSynchronize(sl.stream);
