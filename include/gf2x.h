@@ -208,9 +208,12 @@ typedef struct gf2x_plan gf2x_plan;
 int gf2x_plan_create(gf2x_plan **out, gf2x_ctx *ctx, const gf2x_item *items, uint32_t count, uint64_t *c_base,
                      const uint64_t *a_base, const uint64_t *b_base, uint32_t flags);
 
-/* Enqueue one replay of the plan on `stream`: one graph launch and one event
- * record, independent of the number of items.  Replays on different streams
- * must not overlap (they share the plan's workspace).
+/* Enqueue one replay of the plan on `stream`, with host work independent of
+ * the number of items: for a batch of one size class its kernels are
+ * launched directly (one, or four for a class whose top level is spread over
+ * workgroups), otherwise the graph is launched; then one event record.
+ * Replays on different streams must not overlap (they share the plan's
+ * workspace).
  * Errors: GF2X_EINVAL, GF2X_EDEVICE. */
 int gf2x_plan_launch(gf2x_plan *plan, gf2x_stream_t stream);
 

@@ -794,6 +794,16 @@ int gf2x_plan_create(gf2x_plan **out, gf2x_ctx *ctx, const gf2x_item *items, uin
             delete plan;
             return rc;
         }
+        if (groups.size() == 1) {  // (after record_graph: a staged group may have become direct)
+            plan->one_group = true;
+            plan->cls = groups[0].cls;
+            plan->first = groups[0].first;
+            plan->count = groups[0].count;
+            plan->lds = groups[0].lds;
+            plan->c = c_base;
+            plan->a = a_base;
+            plan->b = b_base;
+        }
     }
     *out = plan;
     return GF2X_OK;
@@ -803,7 +813,17 @@ int gf2x_plan_launch(gf2x_plan *plan, gf2x_stream_t stream) {
     if (!plan) return GF2X_EINVAL;
     if (!plan->g.exec) return GF2X_OK;  // empty batch
     HIP_TRY(hipSetDevice(plan->ctx->device));
-    return replay(plan->g, reinterpret_cast<hipStream_t>(stream));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    if (!plan->one_group) return replay(plan->g, s);
+    // one size class: its kernels (one, or four for a staged class) on the
+    // plan's descriptors, workspace and queue, then the plan's event
+    const Group g{plan->cls, plan->first, plan->count, plan->lds};
+    char *ws = reinterpret_cast<char *>(plan->g.staged_ws);
+    const int rc = launch_one(plan->ctx, g, plan->g.items, ws, plan->c, plan->a, plan->b, s, plan->g.queue);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(plan->g.done, s));
+    plan->g.launched = true;
+    return GF2X_OK;
 }
 
 void gf2x_plan_destroy(gf2x_plan *plan) {

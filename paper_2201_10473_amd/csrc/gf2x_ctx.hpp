@@ -36,6 +36,14 @@ struct GraphEntry {
 struct gf2x_plan {
     gf2x_ctx *ctx = nullptr;
     gf2x::GraphEntry g;
+    // A batch of one size class is replayed by launching its kernels directly
+    // (the graph adds dispatch latency and overlaps nothing); its class group:
+    bool one_group = false;
+    int cls = -1;
+    uint32_t first = 0, count = 0;
+    int lds = 0;
+    uint64_t *c = nullptr;
+    const uint64_t *a = nullptr, *b = nullptr;
 };
 
 struct gf2x_ctx {
