@@ -2,7 +2,7 @@
 
 Workload (one step): 4096 independent dense x dense ring products at
 n = 17669 (277 uint64 words per operand), uniform seeded operands, all in
-one persistent launch (a recorded plan: one HIP graph replay per step).
+one persistent launch (a recorded plan replayed once per step).
 Reported value: products per second over the timed steps, inputs already
 resident in HBM.
 
@@ -14,7 +14,8 @@ roofline: the dominant kernel is the batched product kernel; it is bound by
 VALU integer throughput.  achieved = modelled algorithmic lane-ops of the
 schedule (base-case bit operations plus XOR passes, as reported by
 gf2x_schedule_info) x products per launch / mean launch time, measured with
-HIP events on the launch stream over the timed steps; peak = 256 CU x 4 SIMD
+one pair of HIP events on the launch stream around the timed steps (their
+span over the step count); peak = 256 CU x 4 SIMD
 x 32 lanes per clock x 2.4 GHz = 78.6 T lane-ops/s (a SIMD issues one 32-bit
 wave64 op every two clocks).
 
@@ -74,16 +75,18 @@ def time_batched(ctx, n, count, steps, warmup, seed):
         plan.launch(stream)
         torch.cuda.synchronize()
         done += 1
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    # one pair of HIP events on the launch stream around the timed steps: their
+    # span over the step count is the average launch duration
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s, e in ev:
-        s.record(stream)
+    s_ev.record(stream)
+    for _ in range(steps):
         plan.launch(stream)
-        e.record(stream)
+    e_ev.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    launch_ms = sum(s.elapsed_time(e) for s, e in ev) / steps
+    launch_ms = s_ev.elapsed_time(e_ev) / steps
     plan.close()
     return {"A": A, "B": B, "C": dC, "wall_s": wall, "launch_ms": launch_ms, "items": items}
 
@@ -759,7 +762,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "%d independent dense x dense ring products in F2[X]/(X^%d - 1), uniform seeded "
-            "operands of %d uint64 words, one persistent launch per step (HIP graph replay)"
+            "operands of %d uint64 words, one persistent launch per step (plan replay)"
             % (BATCH, head, (head + 63) // 64),
             "n": head,
             "batch": BATCH,
