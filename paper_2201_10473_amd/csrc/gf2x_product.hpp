@@ -210,15 +210,18 @@ __device__ __forceinline__ void store_full(const u32 *R, u32 n, uint64_t *c) {
 template <class Top>
 __device__ __forceinline__ void staged_eval_item(const DevItem &it, const uint64_t *a_base, const uint64_t *b_base,
                                                  u32 *dst, u32 *smem) {
-    constexpr int S1 = Top::S1, m = Top::m, S = Top::S, PER = 2 * Top::NP * S1;
+    constexpr int S1 = Top::S1, m = Top::m, S = Top::S;
     stage<S>(a_base + it.a_off, b_base + it.b_off, it.n, smem);
     __syncthreads();
     auto part = [&](int x, int p, int j) -> u32 { return (j >= 0 && j < m) ? smem[x * S + p * m + j] : 0u; };
-    for (int idx = tid(); idx < PER; idx += NT) {
-        const int e = idx / (2 * S1);
-        const int r = idx - e * 2 * S1;
-        const int x = r >= S1 ? 1 : 0;
-        dst[idx] = Top::point_word(e, x, r - x * S1, part);
+    // one point at a time, so that each point's combination of parts is fixed
+    // at compile time; point e's pair occupies dst[2 e S1, 2 (e + 1) S1)
+#pragma unroll
+    for (int e = 0; e < Top::NP; ++e) {
+        for (int r = tid(); r < 2 * S1; r += NT) {
+            const int x = r >= S1 ? 1 : 0;
+            dst[e * 2 * S1 + r] = Top::point_word(e, x, r - x * S1, part);
+        }
     }
     __syncthreads();  // smem is reused by the next item
 }
