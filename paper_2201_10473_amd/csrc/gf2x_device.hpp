@@ -667,6 +667,7 @@ struct SeqT3 {
     // address space).  scratch needs INTERP_SCRATCH words; returns the 2S-word
     // product inside scratch.
     static constexpr int INTERP_SCRATCH = R_WORDS + SA_WORDS + UA_WORDS + TMP_WORDS;
+    static constexpr bool INTERP_STORES = false;  // interp_from returns the product
     __device__ __forceinline__ static u32 *interp_from(const u32 *products, u32 *scratch) {
         u32 *out = scratch;
         u32 *Sa = out + R_WORDS;
@@ -830,8 +831,10 @@ struct TopT4 {
     static constexpr int S = 4 * m;
     static constexpr int L = 2 * m;  // words of each coefficient c_i
     static constexpr int TMP_WORDS = 3 * NWAVE;
-    // u, v, c3, c1, c2 (L words each), the product (2S words), scan scratch
-    static constexpr int INTERP_SCRATCH = 5 * L + 2 * S + TMP_WORDS;
+    // u, v, c3, c1, c2 (L words each), the words of the product that the
+    // fold shifts down (S + 2), scan scratch
+    static constexpr int INTERP_SCRATCH = 5 * L + (S + 2) + TMP_WORDS;
+    static constexpr bool INTERP_STORES = true;  // interp_store writes the result
     static constexpr long long BASE = 7 * Child::BASE;
     // evaluation 50*S1 (25 XORs per word of each operand), interpolation
     // about 39 XORs per coefficient word and 6 per product word
@@ -857,16 +860,21 @@ struct TopT4 {
     }
 
     // The seven point products (2*S1 words each, in point order) sit at
-    // products (any address space).  scratch needs INTERP_SCRATCH words;
-    // returns the 2S-word product inside scratch.
-    __device__ __forceinline__ static u32 *interp_from(const u32 *products, u32 *scratch) {
+    // products (any address space).  Interpolates, recombines and stores
+    // the product of n-bit operands at c64: the ring product (kind 0: W(n)
+    // words, the fold r = c + (c >> n)) or the full product (2 W(n) words).
+    // The 2S-word product is never stored whole: its words are formed where
+    // they are used, and only the S + 2 words that the fold shifts down are
+    // staged.  scratch needs INTERP_SCRATCH words.
+    __device__ __forceinline__ static void interp_store(const u32 *products, u32 *scratch, u32 n, u32 kind,
+                                                        uint64_t *c64) {
         u32 *U = scratch;
         u32 *V = U + L;
         u32 *C3 = V + L;
         u32 *C1 = C3 + L;
         u32 *C2 = C1 + L;
-        u32 *out = C2 + L;
-        u32 *tmp = out + 2 * S;
+        u32 *H = C2 + L;
+        u32 *tmp = H + S + 2;
         // word j of point product e, and of a coefficient array, zero outside
         auto P = [&](int e, int j) -> u32 { return (j >= 0 && j < 2 * S1) ? products[e * 2 * S1 + j] : 0u; };
         auto A = [&](const u32 *c, int j) -> u32 { return (j >= 0 && j < L) ? c[j] : 0u; };
@@ -910,8 +918,10 @@ struct TopT4 {
             C2[k] ^= A(C3, k - 1) ^ A(V, k - 2) ^ A(U, k - 3) ^ A(C1, k + 1) ^ A(C1, k - 3);
         __syncthreads();
         scan_xor_stride<L, 2>(C2, tmp);
-        // recomposition: c0 + c1 Y + ... + c6 Y^6, c4 = v + c2, c5 = u + c1
-        for (int r = t; r < 2 * S; r += NT) {
+        // recomposition: word r of c0 + c1 Y + ... + c6 Y^6 (c4 = v + c2,
+        // c5 = u + c1), zero outside [0, 2S)
+        auto word = [&](int r) -> u32 {
+            if (r < 0 || r >= 2 * S) return 0u;
             u32 w = (r < L) ? P(0, r) : 0u;
             w ^= A(C1, r - m);
             w ^= A(C2, r - 2 * m);
@@ -919,10 +929,30 @@ struct TopT4 {
             w ^= A(V, r - 4 * m) ^ A(C2, r - 4 * m);
             w ^= A(U, r - 5 * m) ^ A(C1, r - 5 * m);
             w ^= (r - 6 * m >= 0 && r - 6 * m < L) ? P(6, r - 6 * m) : 0u;
-            out[r] = w;
+            return w;
+        };
+        u32 *c32 = reinterpret_cast<u32 *>(c64);
+        const int W64 = (int)((n + 63u) / 64u);
+        if (kind == 0u) {
+            // ring: out[k] = c[k] + (c >> n)[k], the shifted words staged in H
+            const int w32 = (int)((n + 31u) / 32u);
+            const int q = (int)(n / 32u);
+            const u32 sn = n % 32u;
+            const u32 top = sn ? ((1u << sn) - 1u) : 0xFFFFFFFFu;
+            for (int k = t; k <= w32; k += NT) H[k] = word(k + q);  // w32 <= S
+            __syncthreads();
+            for (int k = t; k < 2 * W64; k += NT) {
+                u32 v = 0;
+                if (k < w32) {
+                    v = word(k) ^ __builtin_amdgcn_alignbit(H[k + 1], H[k], sn);
+                    if (k == w32 - 1) v &= top;
+                }
+                c32[k] = v;
+            }
+        } else {
+            for (int k = t; k < 4 * W64; k += NT) c32[k] = word(k);
         }
         __syncthreads();
-        return out;
     }
 };
 
@@ -1051,7 +1081,7 @@ struct SeqT4 {
         __syncthreads();
     }
 
-    // Divisions and recombination, as in TopT4::interp_from; tmp is the
+    // Divisions and recombination, as in TopT4::interp_store; tmp is the
     // child's scratch (dead now), the 2S-word product goes to out.
     __device__ __forceinline__ static void finish(const u32 (&R)[IRW], u32 *U, u32 *V, u32 *C3, u32 *C1, u32 *C2,
                                                   u32 *tmp, u32 *out) {

@@ -231,10 +231,14 @@ __device__ __forceinline__ void staged_eval_item(const DevItem &it, const uint64
 template <class Top>
 __device__ __forceinline__ void staged_interp_item(const DevItem &it, uint64_t *c_base, const u32 *products,
                                                    u32 *smem) {
-    const u32 *R = Top::interp_from(products, smem);
-    if (it.kind == kKindCyclic) store_cyclic<Top::S>(R, it.n, c_base + it.c_off);
-    else store_full<Top::S>(R, it.n, c_base + it.c_off);
-    __syncthreads();
+    if constexpr (Top::INTERP_STORES) {
+        Top::interp_store(products, smem, it.n, it.kind, c_base + it.c_off);
+    } else {
+        const u32 *R = Top::interp_from(products, smem);
+        if (it.kind == kKindCyclic) store_cyclic<Top::S>(R, it.n, c_base + it.c_off);
+        else store_full<Top::S>(R, it.n, c_base + it.c_off);
+        __syncthreads();
+    }
 }
 
 template <class Sch>

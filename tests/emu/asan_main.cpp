@@ -1,6 +1,6 @@
 // Driver for the emulation harness under AddressSanitizer and
 // UndefinedBehaviorSanitizer (built by tests/test_emulation_asan.py, host
-// code only): products of several schedule classes, a staged class, the
+// code only): products of several schedule classes, two staged classes, the
 // Toeplitz tile and the sparse barrel, each compared with the C oracle.  The
 // LDS stand-in is a heap buffer of the class's exact LDS size, so a kernel
 // reading or writing past its LDS shows up as a heap overflow.  Test
@@ -64,14 +64,18 @@ int main() {
         check("class ring", cls, n, c, rc);
         check("class full", cls, n, f, rf);
     }
-    {
-        const int which = 3;  // a staged Toom-3 class
-        const uint32_t n = 32u * (uint32_t)emu_staged_words(which);
-        auto a = rnd(n), b = rnd(n);
-        std::vector<uint64_t> c(a.size()), rc(a.size());
-        emu_staged(which, a.data(), b.data(), c.data(), n, 0);
-        gf2x_ref_mul_cyclic(rc.data(), a.data(), b.data(), n);
-        check("staged ring", which, n, c, rc);
+    for (int which : {3, 8}) {  // a staged Toom-3 class and a staged Toom-4 class
+        for (uint32_t cut : {0u, 37u}) {
+            const uint32_t n = 32u * (uint32_t)emu_staged_words(which) - cut;
+            auto a = rnd(n), b = rnd(n);
+            std::vector<uint64_t> c(a.size()), rc(a.size()), f(2 * a.size()), rf(2 * a.size());
+            emu_staged(which, a.data(), b.data(), c.data(), n, 0);
+            emu_staged(which, a.data(), b.data(), f.data(), n, 1);
+            gf2x_ref_mul_cyclic(rc.data(), a.data(), b.data(), n);
+            gf2x_ref_mul(rf.data(), a.data(), b.data(), n);
+            check("staged ring", which, n, c, rc);
+            check("staged full", which, n, f, rf);
+        }
     }
     {
         const uint32_t n = 300, count = 9;
