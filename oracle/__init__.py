@@ -16,6 +16,7 @@ from .oracle import (  # noqa: F401
     mul_cyclic,
     mul_batched,
     mul_cyclic_many,
+    mul_cyclic_many_pclmul,
     REF_ITEM_DTYPE,
     words,
 )

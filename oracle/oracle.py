@@ -48,6 +48,8 @@ def load():
         lib.gf2x_ref_fold.argtypes = [_u64p, _u64p, ctypes.c_uint32]
         lib.gf2x_ref_mul_cyclic_many.restype = ctypes.c_int
         lib.gf2x_ref_mul_cyclic_many.argtypes = [_u64p, _u64p, _u64p, ctypes.c_uint32, ctypes.c_uint32]
+        lib.gf2x_ref_mul_cyclic_many_pclmul.restype = ctypes.c_int
+        lib.gf2x_ref_mul_cyclic_many_pclmul.argtypes = [_u64p, _u64p, _u64p, ctypes.c_uint32, ctypes.c_uint32]
         lib.gf2x_ref_mul_batched.restype = ctypes.c_int
         lib.gf2x_ref_mul_batched.argtypes = [_u64p, _u64p, _u64p, ctypes.c_void_p, ctypes.c_uint32]
         lib.gf2x_ref_clmul64.restype = None
@@ -119,6 +121,22 @@ def mul_cyclic_many(a, b, n):
     rc = load().gf2x_ref_mul_cyclic_many(_ptr(r), _ptr(a), _ptr(b), int(n), a.shape[0])
     if rc:
         raise RuntimeError("gf2x_ref_mul_cyclic_many failed (%d)" % rc)
+    return r
+
+
+def mul_cyclic_many_pclmul(a, b, n):
+    """mul_cyclic_many with the CPU's carry-less multiply instruction (for
+    timing the CPU side); None when the CPU lacks it."""
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    b = np.ascontiguousarray(b, dtype=np.uint64)
+    if a.ndim != 2 or a.shape != b.shape or a.shape[1] != words(n):
+        raise ValueError("operands must be (count, words(n)) arrays of equal shape")
+    r = np.zeros_like(a)
+    rc = load().gf2x_ref_mul_cyclic_many_pclmul(_ptr(r), _ptr(a), _ptr(b), int(n), a.shape[0])
+    if rc == -3:
+        return None
+    if rc:
+        raise RuntimeError("gf2x_ref_mul_cyclic_many_pclmul failed (%d)" % rc)
     return r
 
 

@@ -238,6 +238,19 @@ def test_mul_cyclic_many_matches_single():
         assert np.array_equal(R[i], oracle.mul_cyclic(A[i], B[i], n))
 
 
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 1000, 12323])
+def test_pclmul_fast_mode_equals_portable_mode(n):
+    """The timing-only fast mode (PCLMULQDQ) gives the portable oracle's ring
+    products (skipped on a CPU without the instruction)."""
+    A = inputs.dense_batch(n, 4, inputs.SEED_BASE + 97, 0)
+    B = inputs.dense_batch(n, 4, inputs.SEED_BASE + 97, 1)
+    A[:, -1] |= ~inputs.top_mask(n)  # junk above n is ignored by both
+    fast = oracle.mul_cyclic_many_pclmul(A, B, n)
+    if fast is None:
+        pytest.skip("no PCLMULQDQ on this CPU")
+    assert np.array_equal(fast, oracle.mul_cyclic_many(A, B, n))
+
+
 def test_mul_batched_matches_bit_loops():
     """The batched entry point on host arrays: ring, full and sparse items of
     tiny mixed sizes against the bit-by-bit definitions (the sparse operand
