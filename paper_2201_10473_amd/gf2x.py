@@ -123,7 +123,8 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
-            "libgf2x.so is not built (expected at %s); run __graft_entry__.build()" % LIB_PATH
+            "libgf2x.so is not built (expected at %s); build it with "
+            "paper_2201_10473_amd.build.build_library()" % LIB_PATH
         )
     # torch bundles its own HIP runtime under the same soname as the system
     # one.  Importing torch first makes the library bind to that runtime, so
