@@ -758,46 +758,81 @@ struct SeqT3 {
 // the s chains are scanned across the workgroup.  tmp: NWAVE*STRIDE words.
 // Ends with a barrier.
 template <int L, int STRIDE>
-__device__ __forceinline__ void scan_xor_stride(u32 *x, u32 *tmp) {
-    constexpr int C = STRIDE * ((L + NT * STRIDE - 1) / (NT * STRIDE));
-    const int t = tid();
+struct XorScan {
+    static constexpr int C = STRIDE * ((L + NT * STRIDE - 1) / (NT * STRIDE));
     u32 v[C], acc[STRIDE], tot[STRIDE];
+
+    // This thread's C words: local prefixes, then the wave's inclusive
+    // prefix of the per-thread totals; lane 63 leaves the wave total in
+    // tmp[wave * STRIDE + c].
+    __device__ __forceinline__ void up(const u32 *x, u32 *tmp) {
+        const int t = tid();
 #pragma unroll
-    for (int c = 0; c < STRIDE; ++c) acc[c] = 0;
+        for (int c = 0; c < STRIDE; ++c) acc[c] = 0;
 #pragma unroll
-    for (int i = 0; i < C; ++i) {
-        const int k = t * C + i;
-        acc[i % STRIDE] ^= (k < L) ? x[k] : 0u;
-        v[i] = acc[i % STRIDE];
-    }
+        for (int i = 0; i < C; ++i) {
+            const int k = t * C + i;
+            acc[i % STRIDE] ^= (k < L) ? x[k] : 0u;
+            v[i] = acc[i % STRIDE];
+        }
 #pragma unroll
-    for (int c = 0; c < STRIDE; ++c) tot[c] = acc[c];
-    const int lane = t & 63;
+        for (int c = 0; c < STRIDE; ++c) tot[c] = acc[c];
+        const int lane = t & 63;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
+        for (int d = 1; d < 64; d <<= 1) {
 #pragma unroll
-        for (int c = 0; c < STRIDE; ++c) {
-            const u32 o = __shfl_up(acc[c], d, 64);
-            if (lane >= d) acc[c] ^= o;
+            for (int c = 0; c < STRIDE; ++c) {
+                const u32 o = __shfl_up(acc[c], d, 64);
+                if (lane >= d) acc[c] ^= o;
+            }
+        }
+        if (lane == 63) {
+#pragma unroll
+            for (int c = 0; c < STRIDE; ++c) tmp[(t >> 6) * STRIDE + c] = acc[c];
         }
     }
-    const int wave = t >> 6;
-    if (lane == 63) {
+
+    // After a barrier: adds the exclusive prefix of this thread's block.
+    __device__ __forceinline__ void down(u32 *x, const u32 *tmp) {
+        const int t = tid();
+        const int wave = t >> 6;
+        u32 pre[STRIDE];
 #pragma unroll
-        for (int c = 0; c < STRIDE; ++c) tmp[wave * STRIDE + c] = acc[c];
+        for (int c = 0; c < STRIDE; ++c) {
+            pre[c] = acc[c] ^ tot[c];
+            for (int w = 0; w < wave; ++w) pre[c] ^= tmp[w * STRIDE + c];
+        }
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const int k = t * C + i;
+            if (k < L) x[k] = v[i] ^ pre[i % STRIDE];
+        }
     }
+};
+
+template <int L, int STRIDE>
+__device__ __forceinline__ void scan_xor_stride(u32 *x, u32 *tmp) {
+    XorScan<L, STRIDE> sc;
+    sc.up(x, tmp);
     __syncthreads();
-    u32 pre[STRIDE];  // exclusive prefix of this thread's block, per chain
-#pragma unroll
-    for (int c = 0; c < STRIDE; ++c) {
-        pre[c] = acc[c] ^ tot[c];
-        for (int w = 0; w < wave; ++w) pre[c] ^= tmp[w * STRIDE + c];
-    }
-#pragma unroll
-    for (int i = 0; i < C; ++i) {
-        const int k = t * C + i;
-        if (k < L) x[k] = v[i] ^ pre[i % STRIDE];
-    }
+    sc.down(x, tmp);
+    __syncthreads();
+}
+
+// Three independent strided scans (as scan_xor_stride) under one pair of
+// barriers.  tmp: NWAVE*(SA+SB+SC) words.
+template <int L, int SA, int SB, int SC>
+__device__ __forceinline__ void scan_xor_stride3(u32 *a, u32 *b, u32 *c, u32 *tmp) {
+    XorScan<L, SA> sa;
+    XorScan<L, SB> sb;
+    XorScan<L, SC> sc;
+    sa.up(a, tmp);
+    sb.up(b, tmp + NWAVE * SA);
+    sc.up(c, tmp + NWAVE * (SA + SB));
+    __syncthreads();
+    sa.down(a, tmp);
+    sb.down(b, tmp + NWAVE * SA);
+    sc.down(c, tmp + NWAVE * (SA + SB));
     __syncthreads();
 }
 
@@ -1164,6 +1199,264 @@ struct SeqT4 {
         point<6>(T4MemSource<6, Top>{a, b, w32, top}, R, U, V, C3, C1, C2, cin, cs);
         finish(R, U, V, C3, C1, C2, cs, cin);
         return cin;
+    }
+};
+
+// ------------------------------------------------------------- Toom-Cook 5
+// Word-aligned Toom-Cook 5 with x = X^32 (the five-way split with nine
+// products of Section 3, Table compToom), spread over workgroups like TopT4.
+// The paper gives neither points nor interpolation; the construction used:
+//   points 0, 1, x, 1/x, x+1, 1/(x+1), x^2, 1/x^2, inf (the reciprocal points
+//   homogenised: x^4 a(1/x), (x+1)^4 a(1/(x+1)), x^8 a(1/x^2)), so a point
+//   operand has at most m + 8 words;
+//   with c(Y) = c0 + ... + c8 Y^8, the sums E(t) = C(t) + t^8 C(1/t) depend
+//   only on s_k = c_k + c_{8-k}: with s0 = c0 + c8 known,
+//     G(t) = (E(t) + s0 (1+t)^8) / (t (1+t)^2)
+//          = s1 (1 + t^2 + t^4) + s2 (t + t^3) + s3 t^2;
+//   at t = x, x+1, x^2 this 3x3 system is solved by exact divisions only:
+//     K = G(x) + G(x+1) = s3 + s2 x (1+x),
+//     R1 = G(x) + x^2 K,  R3 = G(x^2) + x^4 K,
+//     R3 + x R1 = s1 (1+x+x^2)^2 (1+x) (1+x^2+x^3),
+//     s2 = (R1 + s1 (1+x^2+x^4)) / (x (1+x^3)),  s3 = K + s2 (x + x^2),
+//   where 1/(1+x+x^2)^2 = (1+x^2)/(1+x^6) and 1/(1+x^2+x^3) =
+//   (1+x^2+x^3+x^4)/(1+x^7) (x^3+x^2+1 divides x^7+1), so every division is
+//   a word shift or a strided prefix XOR (scan_xor_stride, s = 1 ... 7);
+//   then c4 = C(1) + s0 + s1 + s2 + s3, and
+//     D(t) = C(t) + c0 + c8 t^8 + s1 t^7 + s2 t^6 + s3 t^5 + c4 t^4
+//   has the form of E(t) + s0 (1+t)^8 with (c1, c2, c3) in place of
+//   (s1, s2, s3): the same solve gives them, and c_{8-k} = s_k + c_k.
+// Every intermediate fits in 2 S1 words (S1 = m + 8).
+template <class Child>
+struct TopT5 {
+    static constexpr bool IS_SEQ = true;
+    static constexpr bool FROM_MEM = false;
+    static constexpr int NP = 9;
+    static constexpr int S1 = Child::S;
+    static constexpr int m = S1 - 8;
+    static constexpr int S = 5 * m;
+    static constexpr int LW = 2 * S1;  // words of every intermediate polynomial
+    static constexpr int TMP_WORDS = 7 * NWAVE;
+    // eight LW-word arrays, the words of the product that the fold shifts
+    // down (S + 2), scan scratch
+    static constexpr int INTERP_SCRATCH = 8 * LW + (S + 2) + TMP_WORDS;
+    static constexpr bool INTERP_STORES = true;  // interp_store writes the result
+    static constexpr long long BASE = 9 * Child::BASE;
+    // evaluation about 44 XORs per word of each operand; interpolation about
+    // 40 XORs per word of each of its LW-word arrays (24 synchronised passes)
+    // and 9 XORs per product word
+    static constexpr long long OPS = 9 * Child::OPS + 88LL * S1 + 40LL * LW + 18LL * S;
+
+    // Word w of operand x of point e, from a source of the parent's words.
+    template <class Part>
+    __device__ __forceinline__ static u32 point_word(int e, int x, int w, const Part &part) {
+        auto p = [&](int q, int j) -> u32 { return part(x, q, j); };
+        // part q times (x+1)^k at word w
+        auto px1 = [&](int q, int k) -> u32 {
+            switch (k) {
+                case 0: return p(q, w);
+                case 1: return p(q, w) ^ p(q, w - 1);
+                case 2: return p(q, w) ^ p(q, w - 2);
+                case 3: return p(q, w) ^ p(q, w - 1) ^ p(q, w - 2) ^ p(q, w - 3);
+                default: return p(q, w) ^ p(q, w - 4);
+            }
+        };
+        switch (e) {
+            case 0: return p(0, w);
+            case 1: return p(0, w) ^ p(1, w) ^ p(2, w) ^ p(3, w) ^ p(4, w);
+            case 2: return p(0, w) ^ p(1, w - 1) ^ p(2, w - 2) ^ p(3, w - 3) ^ p(4, w - 4);
+            case 3: return p(0, w - 4) ^ p(1, w - 3) ^ p(2, w - 2) ^ p(3, w - 1) ^ p(4, w);
+            case 4: return px1(0, 0) ^ px1(1, 1) ^ px1(2, 2) ^ px1(3, 3) ^ px1(4, 4);
+            case 5: return px1(0, 4) ^ px1(1, 3) ^ px1(2, 2) ^ px1(3, 1) ^ px1(4, 0);
+            case 6: return p(0, w) ^ p(1, w - 2) ^ p(2, w - 4) ^ p(3, w - 6) ^ p(4, w - 8);
+            case 7: return p(0, w - 8) ^ p(1, w - 6) ^ p(2, w - 4) ^ p(3, w - 2) ^ p(4, w);
+            default: return p(4, w);
+        }
+    }
+
+    // For 0 <= j < LW: f(j, v) computes NO values, then dst[o][j] = v[o];
+    // every value is computed before any is stored, so f may read the
+    // destination arrays at any index.  Ends with a barrier.
+    template <int NO, class F>
+    __device__ __forceinline__ static void xpass(u32 *const (&dst)[NO], F f) {
+        constexpr int IT = (LW + NT - 1) / NT;
+        u32 v[IT][NO];
+        const int t = tid();
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int j = t + i * NT;
+#pragma unroll
+            for (int o = 0; o < NO; ++o) v[i][o] = 0u;
+            if (j < LW) f(j, v[i]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < IT; ++i) {
+            const int j = t + i * NT;
+            if (j < LW) {
+#pragma unroll
+                for (int o = 0; o < NO; ++o) dst[o][j] = v[i][o];
+            }
+        }
+        __syncthreads();
+    }
+
+    __device__ __forceinline__ static u32 A(const u32 *c, int j) { return (j >= 0 && j < LW) ? c[j] : 0u; }
+
+    // Given G(x), G(x+1), G(x^2) of the form s1 (1+t^2+t^4) + s2 (t+t^3) +
+    // s3 t^2 in gx, gx1, gx2, leaves s1 in gx2, s2 in gx and s3 in k.  K, R1
+    // and (R3 + x R1)(1 + x^2) are formed in one pass from the G arrays.
+    template <bool ADD>
+    __device__ __forceinline__ static void solve3(u32 *gx, u32 *gx1, u32 *gx2, u32 *k, u32 *tmp,
+                                                  u32 *const (&add)[3]) {
+        auto K = [&](int i) -> u32 { return A(gx, i) ^ A(gx1, i); };
+        auto R1 = [&](int i) -> u32 { return A(gx, i) ^ K(i - 2); };
+        auto N = [&](int i) -> u32 { return A(gx2, i) ^ K(i - 4) ^ R1(i - 1); };
+        {
+            u32 *const out[3] = {k, gx, gx2};
+            xpass(out, [&](int j, u32 (&v)[3]) {
+                v[0] = K(j);
+                v[1] = R1(j);
+                v[2] = N(j) ^ N(j - 2);  // (R3 + x R1) (1 + x^2)
+            });
+        }
+        scan_xor_stride<LW, 6>(gx2, tmp);
+        scan_xor_stride<LW, 1>(gx2, tmp);
+        {
+            u32 *const out[1] = {gx2};
+            xpass(out, [&](int j, u32 (&v)[1]) { v[0] = gx2[j] ^ A(gx2, j - 2) ^ A(gx2, j - 3) ^ A(gx2, j - 4); });
+        }
+        scan_xor_stride<LW, 7>(gx2, tmp);  // s1
+        {
+            // s2 = (R1 + s1 (1 + x^2 + x^4)) / x / (1 + x^3)
+            u32 *const out[1] = {gx};
+            xpass(out, [&](int j, u32 (&v)[1]) {
+                const int i = j + 1;
+                v[0] = A(gx, i) ^ A(gx2, i) ^ A(gx2, i - 2) ^ A(gx2, i - 4);
+            });
+        }
+        scan_xor_stride<LW, 3>(gx, tmp);  // s2
+        if constexpr (ADD) {
+            // also add s1, s2, s3 into the arrays at add (in that order)
+            u32 *const out[4] = {k, add[0], add[1], add[2]};
+            xpass(out, [&](int j, u32 (&v)[4]) {
+                v[0] = k[j] ^ A(gx, j - 1) ^ A(gx, j - 2);
+                v[1] = add[0][j] ^ gx2[j];
+                v[2] = add[1][j] ^ gx[j];
+                v[3] = add[2][j] ^ v[0];
+            });
+        } else {
+            u32 *const out[1] = {k};
+            xpass(out, [&](int j, u32 (&v)[1]) { v[0] = k[j] ^ A(gx, j - 1) ^ A(gx, j - 2); });  // s3
+        }
+    }
+
+    // The nine point products (2*S1 words each, in point order) sit at
+    // products (any address space).  Interpolates, recombines and stores the
+    // product of n-bit operands at c64: the ring product (kind 0: W(n)
+    // words) or the full product (2 W(n) words), as TopT4::interp_store.
+    __device__ __forceinline__ static void interp_store(const u32 *products, u32 *scratch, u32 n, u32 kind,
+                                                        uint64_t *c64) {
+        u32 *a0 = scratch;
+        u32 *a1 = a0 + LW;
+        u32 *a2 = a1 + LW;
+        u32 *a3 = a2 + LW;
+        u32 *a4 = a3 + LW;
+        u32 *a5 = a4 + LW;
+        u32 *a6 = a5 + LW;
+        u32 *a7 = a6 + LW;
+        u32 *H = a7 + LW;
+        u32 *tmp = H + S + 2;
+        auto P = [&](int e, int j) -> u32 { return (j >= 0 && j < 2 * S1) ? products[e * 2 * S1 + j] : 0u; };
+        auto s0 = [&](int j) -> u32 { return P(0, j) ^ P(8, j); };
+        // Every read of the products, in one pass: E(t) + s0 (1+t)^8 at t = x,
+        // x+1, x^2 divided at once by x, x^2, x^2 (word shifts) into a0..a2,
+        // and the parts of c4 and of D(t) that the products give: C(1) + s0
+        // into a4, D(t) less its c4..c7 terms at t = x, x+1, x^2 into a5..a7.
+        {
+            auto E0 = [&](int i) -> u32 { return P(2, i) ^ P(3, i) ^ s0(i) ^ s0(i - 8); };
+            auto E1 = [&](int i) -> u32 { return P(4, i) ^ P(5, i) ^ s0(i - 8); };
+            auto E2 = [&](int i) -> u32 { return P(6, i) ^ P(7, i) ^ s0(i) ^ s0(i - 16); };
+            u32 *const out[7] = {a0, a1, a2, a4, a5, a6, a7};
+            xpass(out, [&](int j, u32 (&v)[7]) {
+                v[0] = E0(j + 1);
+                v[1] = E1(j + 2);
+                v[2] = E2(j + 2);
+                v[3] = P(1, j) ^ s0(j);
+                v[4] = P(2, j) ^ P(0, j) ^ P(8, j - 8);
+                v[5] = P(4, j) ^ s0(j) ^ P(8, j - 8);
+                v[6] = P(6, j) ^ P(0, j) ^ P(8, j - 16);
+            });
+        }
+        // then by 1 + x^2, 1 + x and 1 + x^4: G(t)
+        scan_xor_stride3<LW, 2, 1, 4>(a0, a1, a2, tmp);
+        u32 *const none[3] = {nullptr, nullptr, nullptr};
+        solve3<false>(a0, a1, a2, a3, tmp, none);  // s1 = a2, s2 = a0, s3 = a3
+        const u32 *s1 = a2, *s2 = a0, *s3 = a3;
+        // c4 = C(1) + s0 + s1 + s2 + s3 into a4, and q = (1 + x^2) s1 +
+        // (1 + x) s2 + s3 into a1, so that s1 (x+1)^7 + s2 (x+1)^6 + s3 (x+1)^5
+        // = (1 + x)(1 + x^4) q
+        {
+            u32 *const out[2] = {a4, a1};
+            xpass(out, [&](int j, u32 (&v)[2]) {
+                const u32 t3 = s1[j] ^ s2[j] ^ s3[j];
+                v[0] = a4[j] ^ t3;
+                v[1] = t3 ^ A(s1, j - 2) ^ A(s2, j - 1);
+            });
+        }
+        // D(t) at x, x+1, x^2, divided by the same word shifts, into a5, a1, a7
+        {
+            const u32 *c4 = a4, *q = a1;
+            u32 *const out[3] = {a5, a1, a7};
+            xpass(out, [&](int j, u32 (&v)[3]) {
+                int i = j + 1;
+                v[0] = A(a5, i) ^ A(s1, i - 7) ^ A(s2, i - 6) ^ A(s3, i - 5) ^ A(c4, i - 4);
+                i = j + 2;
+                v[1] = A(a6, i) ^ A(c4, i) ^ A(c4, i - 4) ^ A(q, i) ^ A(q, i - 1) ^ A(q, i - 4) ^ A(q, i - 5);
+                v[2] = A(a7, i) ^ A(s1, i - 14) ^ A(s2, i - 12) ^ A(s3, i - 10) ^ A(c4, i - 8);
+            });
+        }
+        scan_xor_stride3<LW, 2, 1, 4>(a5, a1, a7, tmp);
+        // c1 = a7, c2 = a5, c3 = a6; c7 = s1 + c1, c6 = s2 + c2 and
+        // c5 = s3 + c3 replace s1, s2, s3 in a2, a0, a3
+        u32 *const sums[3] = {a2, a0, a3};
+        solve3<true>(a5, a1, a7, a6, tmp, sums);
+        const int t = tid();
+        // recomposition: word r of c0 + c1 Y + ... + c8 Y^8 (Y = x^m); zero
+        // outside [0, 2S)
+        auto word = [&](int r) -> u32 {
+            if (r < 0 || r >= 2 * S) return 0u;
+            u32 w = P(0, r);
+            w ^= A(a7, r - m);
+            w ^= A(a5, r - 2 * m);
+            w ^= A(a6, r - 3 * m);
+            w ^= A(a4, r - 4 * m);
+            w ^= A(a3, r - 5 * m);
+            w ^= A(a0, r - 6 * m);
+            w ^= A(a2, r - 7 * m);
+            w ^= P(8, r - 8 * m);
+            return w;
+        };
+        u32 *c32 = reinterpret_cast<u32 *>(c64);
+        const int W64 = (int)((n + 63u) / 64u);
+        if (kind == 0u) {
+            const int w32 = (int)((n + 31u) / 32u);
+            const int q = (int)(n / 32u);
+            const u32 sn = n % 32u;
+            const u32 top = sn ? ((1u << sn) - 1u) : 0xFFFFFFFFu;
+            for (int k = t; k <= w32; k += NT) H[k] = word(k + q);  // w32 <= S
+            __syncthreads();
+            for (int k = t; k < 2 * W64; k += NT) {
+                u32 v = 0;
+                if (k < w32) {
+                    v = word(k) ^ __builtin_amdgcn_alignbit(H[k + 1], H[k], sn);
+                    if (k == w32 - 1) v &= top;
+                }
+                c32[k] = v;
+            }
+        } else {
+            for (int k = t; k < 4 * W64; k += NT) c32[k] = word(k);
+        }
+        __syncthreads();
     }
 };
 

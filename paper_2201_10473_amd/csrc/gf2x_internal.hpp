@@ -11,7 +11,7 @@
 namespace gf2x {
 
 constexpr int kNumDirect = 41;   // classes computed inside one workgroup
-constexpr int kNumClasses = 50;  // plus the staged classes
+constexpr int kNumClasses = 52;  // plus the staged classes
 constexpr uint32_t kKindCyclic = 0;
 constexpr uint32_t kKindFull = 1;
 constexpr uint32_t kKindSparse = 2;  // low byte of the kind; the weight is kind >> 8

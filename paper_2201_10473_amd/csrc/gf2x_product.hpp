@@ -68,6 +68,8 @@ using Class40 = SeqT3<Class22, true>;
 using Top4Class9 = TopT4<Class9>;
 using Top4Class22 = TopT4<Class22>;
 using Top4Class24 = TopT4<Class24>;
+using Top5Class22 = TopT5<Class22>;
+using Top5Class24 = TopT5<Class24>;
 
 // X(id, name, schedule type)
 #define GF2X_CLASS_LIST(X) \
@@ -128,7 +130,9 @@ using Top4Class24 = TopT4<Class24>;
     X(46, "G.T3.T3.T3.K2^5.U5", Class20, 15, Class15) \
     X(47, "G.T4.T3.K2^5.U5", Top4Class9, 9, Class9) \
     X(48, "G.T4.T3.K2^5.U4", Top4Class22, 22, Class22) \
-    X(49, "G.T4.K2^5.U9", Top4Class24, 24, Class24)
+    X(49, "G.T4.K2^5.U9", Top4Class24, 24, Class24) \
+    X(50, "G.T5.T3.K2^5.U4", Top5Class22, 22, Class22) \
+    X(51, "G.T5.K2^5.U9", Top5Class24, 24, Class24)
 
 #define GF2X_COUNT_CLASS(id, name, T) +1
 constexpr int NUM_CLASSES = 0 GF2X_CLASS_LIST(GF2X_COUNT_CLASS);

@@ -1,6 +1,6 @@
 // Driver for the emulation harness under AddressSanitizer and
 // UndefinedBehaviorSanitizer (built by tests/test_emulation_asan.py, host
-// code only): products of several schedule classes, two staged classes, the
+// code only): products of several schedule classes, three staged classes, the
 // Toeplitz tile and the sparse barrel, each compared with the C oracle.  The
 // LDS stand-in is a heap buffer of the class's exact LDS size, so a kernel
 // reading or writing past its LDS shows up as a heap overflow.  Test
@@ -64,7 +64,7 @@ int main() {
         check("class ring", cls, n, c, rc);
         check("class full", cls, n, f, rf);
     }
-    for (int which : {3, 8}) {  // a staged Toom-3 class and a staged Toom-4 class
+    for (int which : {3, 8, 10}) {  // staged Toom-3, Toom-4 and Toom-5 classes
         for (uint32_t cut : {0u, 37u}) {
             const uint32_t n = 32u * (uint32_t)emu_staged_words(which) - cut;
             auto a = rnd(n), b = rnd(n);

@@ -79,11 +79,11 @@ def test_toeplitz_tile(emu, n, count):
         assert np.array_equal(C[i], oracle.mul_cyclic(h, R[i], n)), i
 
 
-@pytest.mark.parametrize("which", [0, 3, 4, 6, 7, 8])
+@pytest.mark.parametrize("which", [0, 3, 4, 6, 7, 8, 9, 10])
 def test_staged_top_level(emu, which):
-    """Top Toom-3 (which < 6) or Toom-4 (which >= 6) level spread over
-    workgroups: evaluation words, the five or seven point products by the
-    child class, interpolation and fold."""
+    """Top Toom-3 (which < 6), Toom-4 (6 <= which < 9) or Toom-5 (which >= 9)
+    level spread over workgroups: evaluation words, the five, seven or nine
+    point products by the child class, interpolation and fold."""
     u64p = ctypes.POINTER(ctypes.c_uint64)
     S = emu.emu_staged_words(which)
     for n in (S * 32, S * 32 - 37):

@@ -119,6 +119,7 @@ ALL_CLASSES = [
     ("G.T3.T3.K2^5.U4", 1128), ("G.T3.T3.K2^5.U5", 1416), ("G.T3.T3.K2^5.U7", 1992), ("G.T3.K2^5.U6", 570),
     ("G.T3.K2^5.U9", 858), ("G.T3.T3.T3.K2^5.U5", 4242),
     ("G.T4.T3.K2^5.U5", 1884), ("G.T4.T3.K2^5.U4", 1500), ("G.T4.K2^5.U9", 1140),
+    ("G.T5.T3.K2^5.U4", 1850), ("G.T5.K2^5.U9", 1400),
 ]
 
 
