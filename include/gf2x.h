@@ -13,7 +13,7 @@
  *   - Appendix A (Karatsuba 2-, 3- and 5-way splits), Section 3 with
  *     Appendix D (word-aligned Toom-Cook 3 with evaluation points 0, 1, x,
  *     x+1, infinity and exact divisions by x and x+1) and the Toom-Cook 4
- *     split of Section 3 (7 products) are the recursions the GPU kernels
+ *     and 5 splits of Section 3 (7 and 9 products) are the recursions the GPU kernels
  *     implement; a measured per-size table picks among them, and the result
  *     does not depend on the choice.
  *   - Section 1 (sparse-dense products of HQC and BIKE): a dense operand
