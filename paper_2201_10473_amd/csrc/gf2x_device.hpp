@@ -290,11 +290,15 @@ __device__ __forceinline__ void k2_merge(const u32 *src, u32 *dst) {
 // Down pass: the root split reads the source; level L is stored in DA when
 // D-1-L is even, else in DB (so level D-1 lands in DA).  The units read
 // their operands from level D-1, i.e. they perform the last split while
-// loading.  The last merge is fused too: after every unit has loaded its
-// operands, level D-1 is cleared and each unit XORs its product into its
-// parent's product in place (LDS atomics), at offset T*k for child k:
+// loading (child 0 reads the low halves of its parent's operands, child 1
+// the high halves, child 2 both).  The last merge is fused too: after every
+// unit has loaded its operands, each unit writes its product into its
+// parent's product in place, at offset T*k for child k:
 //   child 0 and 1 add [c_lo, c_lo + c_hi, c_hi], child 2 adds [c_lo, c_hi]
 // (the KaratRec reconstruction, distributed over the three children).  The
+// words that one child alone covers, and child 2's middle words, are plain
+// stores; after a barrier children 0 and 1 add into the middle (LDS atomics),
+// so level D-1 needs no clearing.  The
 // up pass then alternates DA -> DB -> DA ... with the same parity rule, and
 // every buffer written is dead at that point.
 template <int D, int T>
@@ -348,8 +352,8 @@ struct ParK2 {
         }
     }
 
-    // The unit phase: load (last split), clear level D-1, multiply, XOR the
-    // product into the parent (last merge).  Source Src is only used for D == 1.
+    // The unit phase: load (last split), multiply, write the product into
+    // the parent (last merge).  Source Src is only used for D == 1.
     template <class Src>
     __device__ __forceinline__ static void units(const Src &src, u32 *DA) {
         const int u = tid();
@@ -357,36 +361,56 @@ struct ParK2 {
         const int v = u / 3, k = u - 3 * (u / 3);
         u32 a[T], b[T], c[2 * T];
         if (active) {
+            if constexpr (D == 1) {
 #pragma unroll
-            for (int w = 0; w < T; ++w) {
-                u32 alo, ahi, blo, bhi;
-                if constexpr (D == 1) {
-                    alo = src.get(0, w);
-                    ahi = src.get(0, T + w);
-                    blo = src.get(1, w);
-                    bhi = src.get(1, T + w);
-                } else {
-                    const u32 *node = DA + v * NS;  // [a_v (2T) | b_v (2T)]
-                    alo = node[w];
-                    ahi = node[T + w];
-                    blo = node[2 * T + w];
-                    bhi = node[3 * T + w];
+                for (int w = 0; w < T; ++w) {
+                    const u32 alo = src.get(0, w), ahi = src.get(0, T + w);
+                    const u32 blo = src.get(1, w), bhi = src.get(1, T + w);
+                    a[w] = (k != 1 ? alo : 0u) ^ (k != 0 ? ahi : 0u);
+                    b[w] = (k != 1 ? blo : 0u) ^ (k != 0 ? bhi : 0u);
                 }
-                a[w] = (k != 1 ? alo : 0u) ^ (k != 0 ? ahi : 0u);
-                b[w] = (k != 1 ? blo : 0u) ^ (k != 0 ? bhi : 0u);
+            } else {
+                // [a_v (2T) | b_v (2T)]: unit 0 takes the low halves, unit 1
+                // the high halves, unit 2 their sums
+                const u32 *node = DA + v * NS;
+                const u32 *half = node + (k == 1 ? T : 0);
+#pragma unroll
+                for (int w = 0; w < T; ++w) {
+                    a[w] = half[w];
+                    b[w] = half[2 * T + w];
+                }
+                if (k == 2) {
+#pragma unroll
+                    for (int w = 0; w < T; ++w) {
+                        a[w] ^= node[T + w];
+                        b[w] ^= node[3 * T + w];
+                    }
+                }
             }
         }
         __syncthreads();
-        for (int i = tid(); i < DA_WORDS; i += NT) DA[i] = 0;
-        __syncthreads();
+        // Node v's product (4T words) replaces its operands.  Child 0 alone
+        // writes words [0, T), child 1 alone [3T, 4T); child 2 first stores
+        // its [c_lo, c_hi] over the middle [T, 3T), then children 0 and 1 add
+        // theirs there.
+        u32 *node = DA + v * NS;
         if (active) {
             unit_mul<T>(a, b, c);
-            u32 *q = DA + v * NS + T * (k < 2 ? k : 1);
+            u32 *own = node + (k == 0 ? 0 : k == 1 ? 3 * T : T);
+#pragma unroll
+            for (int w = 0; w < T; ++w) own[w] = k == 1 ? c[T + w] : c[w];
+            if (k == 2) {
+#pragma unroll
+                for (int w = 0; w < T; ++w) node[2 * T + w] = c[T + w];
+            }
+        }
+        __syncthreads();
+        if (active && k < 2) {
 #pragma unroll
             for (int w = 0; w < T; ++w) {
-                lds_xor(q + w, c[w]);
-                lds_xor(q + T + w, k < 2 ? (c[w] ^ c[T + w]) : c[T + w]);
-                if (k < 2) lds_xor(q + 2 * T + w, c[T + w]);
+                const u32 mid = c[w] ^ c[T + w];
+                lds_xor(node + T + w, k == 0 ? mid : c[w]);
+                lds_xor(node + 2 * T + w, k == 0 ? c[T + w] : mid);
             }
         }
         __syncthreads();
