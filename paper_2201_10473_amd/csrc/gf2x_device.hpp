@@ -1264,6 +1264,9 @@ struct TopT5 {
     // down (S + 2), scan scratch
     static constexpr int INTERP_SCRATCH = 8 * LW + (S + 2) + TMP_WORDS;
     static constexpr bool INTERP_STORES = true;  // interp_store writes the result
+    // its interpolation kernel keeps to 80 VGPRs, so that six workgroups fit
+    // a CU where the LDS allows it (the Toom-5 classes use about 86 otherwise)
+    static constexpr int INTERP_WAVES = 6;
     static constexpr long long BASE = 9 * Child::BASE;
     // evaluation about 44 XORs per word of each operand; interpolation about
     // 40 XORs per word of each of its LW-word arrays (24 synchronised passes)

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "gf2x_launch.hpp"
 #include "gf2x_product.hpp"
 
@@ -22,8 +24,19 @@ __global__ __launch_bounds__(NT) void k_stage_eval(const DevItem *items, u32 cou
 
 // Interpolation of the NP point products of each item, then the ring fold
 // or the full store (persistent workgroups).
+// Waves per SIMD the interpolation kernel of Top must allow (a register
+// budget for the compiler): Top::INTERP_WAVES where a Top declares it.
+template <class T, class = void>
+struct InterpWaves {
+    static constexpr int value = 1;
+};
+template <class T>
+struct InterpWaves<T, std::void_t<decltype(T::INTERP_WAVES)>> {
+    static constexpr int value = T::INTERP_WAVES;
+};
+
 template <class Top>
-__global__ __launch_bounds__(NT) void k_stage_interp(const DevItem *items, u32 count, uint64_t *c_base,
+__global__ __launch_bounds__(NT, InterpWaves<Top>::value) void k_stage_interp(const DevItem *items, u32 count, uint64_t *c_base,
                                                      const u32 *ws_out) {
     extern __shared__ u32 smem[];
     for (u32 i = blockIdx.x; i < count; i += gridDim.x)
